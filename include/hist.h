@@ -1,0 +1,244 @@
+/*
+ * hist.h -- C ABI of the MI355X (gfx950) histogram-filling library.
+ *
+ * The library fills ROOT-style histograms on the GPU: for every event it finds
+ * the bin on each axis, adds the event weight and its square to that bin, and
+ * updates the statistics sums.  This is the Fill operation of arXiv:2401.13310
+ * Sec. 3.1 (find bin with underflow/overflow bins, increment by a weight,
+ * update the sums behind mean and standard deviation), with the statistics as
+ * the transform-reduce sums of Sec. 3.2 and sums that accumulate across
+ * bulks as required in Sec. 3.3.  A histogram object owns its device
+ * allocations and takes bulks of events, and the result is copied back only
+ * when it is read (Sec. 3.2).
+ *
+ * Conventions (shared with every entry point):
+ *   - Bins: on an axis with n bins, bin 0 is underflow, bins 1..n are the
+ *     in-range bins and bin n+1 is overflow.  Bins include their lower edge.
+ *     Fixed-width axes use 1 + floor(n (x - xmin) / (xmax - xmin)) evaluated
+ *     in IEEE binary64 left to right, clamped to n; variable axes return the
+ *     number of edges e_i with !(x < e_i) (upper_bound).  NaN goes to
+ *     overflow.  FP32 coordinates are widened exactly to binary64 first.
+ *   - Global bin: g = b0 + (n0+2) * (b1 + (n1+2) * b2), x fastest; the total
+ *     bin count is T = prod(n_a + 2), at most 2^31 - 1.
+ *   - Statistics (events inside the range on every axis only):
+ *       d=1 [Sw, Sw2, Swx, Swx2]
+ *       d=2 [Sw, Sw2, Swx, Swx2, Swy, Swy2, Swxy]
+ *       d=3 [Sw, Sw2, Swx, Swx2, Swy, Swy2, Swxy, Swz, Swz2, Swxz, Swyz]
+ *     S = 2 + 2d + d(d-1)/2 values.  entries counts every event.
+ *   - Streams are hipStream_t values passed as void* (NULL = null stream).
+ *     Calls marked "asynchronous" enqueue work on the stream and return; the
+ *     caller keeps every input buffer alive and unmodified until the stream
+ *     has passed the call.  They never synchronize the device.
+ *   - Device pointers are plain HIP device addresses (e.g. a torch tensor's
+ *     data_ptr()).  Host pointers are ordinary process memory.
+ *   - Every function returns a hist_status; on error the handle is left as it
+ *     was and hist_last_error() holds a message for the calling thread.
+ *   - A handle may be used from one stream at a time.
+ */
+#ifndef HIST_H
+#define HIST_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define HIST_API __attribute__((visibility("default")))
+#else
+#define HIST_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hist_s hist_t;
+typedef struct hist_batch_s hist_batch_t;
+
+typedef enum {
+    HIST_OK = 0,
+    HIST_EINVAL = 1,    /* invalid argument                                 */
+    HIST_ENOMEM = 2,    /* device or host allocation failed                 */
+    HIST_EDEVICE = 3,   /* a HIP call failed (message in hist_last_error)   */
+    HIST_ECAPTURE = 4,  /* a synchronizing call during stream capture       */
+    HIST_ENOTSUP = 5    /* combination not supported                         */
+} hist_status;
+
+typedef enum { HIST_F64 = 0, HIST_F32 = 1 } hist_dtype;
+
+/* One axis.  edges == NULL: nbins fixed-width bins on [xmin, xmax), both
+ * finite, xmin < xmax.  Otherwise edges is a HOST pointer to nbins+1 finite,
+ * strictly increasing values (copied by hist_create); xmin/xmax are ignored. */
+typedef struct {
+    int32_t nbins;
+    double xmin, xmax;
+    const double *edges;
+} hist_axis;
+
+/* hist_create flags */
+#define HIST_F_ACC_F32C   (1u << 0)  /* FP32 fills accumulate in compensated FP32 LDS
+                                        sums (TwoSum error terms for w and w^2),
+                                        merged in FP64; otherwise FP32 inputs are
+                                        accumulated in FP64 like FP64 inputs        */
+#define HIST_F_LEARNED    (1u << 1)  /* train the learned find-bin index of every
+                                        variable axis at creation (hist_train_index) */
+
+/* Accumulation strategies (hist_set_strategy / hist_plan_info).  */
+typedef enum {
+    HIST_STRAT_AUTO = 0,    /* heuristic, or the autotuner's choice after hist_tune   */
+    HIST_STRAT_LDS = 1,     /* LDS-privatized window of bins, out-of-window events use
+                               global atomics                                          */
+    HIST_STRAT_GLOBAL = 2,  /* global atomics only                                     */
+    HIST_STRAT_TILED = 3    /* bins computed once into a scratch array, then bin-range
+                               tiles accumulated in LDS                                */
+} hist_strategy;
+
+/* Search used on a variable axis. */
+typedef enum {
+    HIST_SEARCH_BINARY = 0,   /* binary search over the edges (always available)  */
+    HIST_SEARCH_LEARNED = 1   /* learned index + exact bounded search (needs
+                                 hist_train_index)                                 */
+} hist_search;
+
+/* ---- lifecycle ---------------------------------------------------------- */
+
+/* Creates a histogram on the current HIP device.  dims in 1..3, axes[dims].
+ * Allocates and zeroes the device bin arrays, statistics and scratch.
+ * Errors: HIST_EINVAL (bad axes, T > 2^31-1, out == NULL), HIST_ENOMEM,
+ * HIST_EDEVICE.  Synchronizes the device once (creation is not a hot call). */
+HIST_API hist_status hist_create(int dims, const hist_axis *axes, uint32_t flags, hist_t **out);
+
+/* Frees everything the handle owns.  NULL is accepted.  Synchronizes. */
+HIST_API hist_status hist_destroy(hist_t *h);
+
+/* ---- the hot path ---------------------------------------------------------- */
+
+/* Fill n events (Sec. 3.1 steps 1-3), adding to earlier fills (Sec. 3.3).
+ * coords: HOST array of dims DEVICE pointers; coords[a][i] is coordinate a of
+ * event i, n contiguous values of `dtype` each.  weights: DEVICE pointer to n
+ * values of `dtype`, or NULL for unit weights.  n == 0 is a no-op.
+ * Asynchronous on `stream`; allocates nothing; capture-safe.
+ * Errors: HIST_EINVAL (NULL handle, n < 0, NULL coordinate with n > 0,
+ * HIST_F32C accumulation requested with FP64 inputs is not an error -- FP64
+ * inputs always accumulate in FP64), HIST_EDEVICE (launch failure). */
+HIST_API hist_status hist_fill(hist_t *h, const void *const *coords, const void *weights,
+                      int64_t n, hist_dtype dtype, void *stream);
+
+/* Find-bin only (Sec. 3.1 step 1 plus the global-bin linearization): writes
+ * the global bin of each event to bins_dev (DEVICE, n int32).  Same search
+ * and arithmetic as hist_fill.  Asynchronous; allocates nothing. */
+HIST_API hist_status hist_findbin(hist_t *h, const void *const *coords, int64_t n, hist_dtype dtype,
+                         int32_t *bins_dev, void *stream);
+
+/* ---- reading (the only synchronizing calls) -------------------------------- */
+
+/* Statistics (layout above) into HOST out[cap]; *count = S.  cap < S:
+ * nothing is written, *count = S, HIST_EINVAL.  Synchronizes `stream`;
+ * HIST_ECAPTURE while the stream is capturing. */
+HIST_API hist_status hist_stats(hist_t *h, double *out, int cap, int *count, void *stream);
+
+/* Bin sums of weights and of squared weights (HOST, T doubles each, either may
+ * be NULL) and the entry count (HOST, may be NULL).  Synchronizes `stream`;
+ * HIST_ECAPTURE while capturing. */
+HIST_API hist_status hist_read(hist_t *h, double *sumw, double *sumw2, int64_t *entries, void *stream);
+
+/* Zero bins, statistics and entries.  Asynchronous (fill kernels, no memset). */
+HIST_API hist_status hist_reset(hist_t *h, void *stream);
+
+/* ---- learned find-bin index --------------------------------------------- */
+
+/* Trains the learned index of variable axis `axis` on the GPU: pairs
+ * (x, bin) made from the edge array by the find-bin rule (each edge e_i and
+ * each bin midpoint), a per-segment quadratic least-squares model of the bin
+ * position over an order-preserving feature of x, and per-segment error
+ * bounds measured at every edge.  The bounds make the bounded search exact:
+ * after training, hist_fill and hist_findbin on this axis give the same bins
+ * as binary search, bit for bit.  Switches the axis to HIST_SEARCH_LEARNED.
+ * Synchronizes `stream`.  Errors: HIST_EINVAL (axis not variable). */
+HIST_API hist_status hist_train_index(hist_t *h, int axis, void *stream);
+
+/* Selects the search of a variable axis (HIST_SEARCH_LEARNED needs a trained
+ * index, else HIST_EINVAL). */
+HIST_API hist_status hist_set_search(hist_t *h, int axis, hist_search mode);
+
+/* Describes a trained index: segments, feature kind (0 key bits, 1 linear),
+ * mean and max candidate-window width over segments (bins). */
+HIST_API hist_status hist_index_info(hist_t *h, int axis, int *segments, int *feature,
+                            double *mean_window, double *max_window);
+
+/* ---- plans and autotuning ------------------------------------------------- */
+
+/* Forces a plan for later fills: strategy (hist_strategy), blocks (0 = auto),
+ * subhists = LDS copies per block for small histograms (0 = auto).  Used by
+ * tests to show every strategy gives the same result. */
+HIST_API hist_status hist_set_strategy(hist_t *h, int strategy, int blocks, int subhists);
+
+/* Autotuner: times the candidate plans on the given sample with HIP events on
+ * `stream`, keeps the fastest for this histogram shape and remembers it in a
+ * process-wide cache keyed by the shape.  It also picks the LDS window of bins
+ * with the largest sample mass.  The histogram contents are restored to what
+ * they were before the call.  Synchronizes; HIST_ECAPTURE while capturing. */
+HIST_API hist_status hist_tune(hist_t *h, const void *const *coords, const void *weights, int64_t n,
+                      hist_dtype dtype, void *stream);
+
+/* Plan the next fill of n events would use: strategy, blocks, LDS copies,
+ * window start and size (bins), accumulator (0 u32, 1 u16, 2 f64, 3 f32c). */
+HIST_API hist_status hist_plan_info(hist_t *h, int64_t n, hist_dtype dtype, int weighted,
+                           int *strategy, int *blocks, int *subhists, int64_t *window_lo,
+                           int64_t *window_len, int *accumulator);
+
+/* Fixes, for later fills, the first bin of the LDS window (-1 = the
+ * autotuner's or heuristic choice) and the merge of LDS windows (-1 auto,
+ * 0 coalesced global atomics, 1 staging buffer plus reduction kernel).  Used
+ * by tests and benchmarks to pin a plan. */
+HIST_API hist_status hist_set_window(hist_t *h, int64_t window_lo, int merge);
+
+/* Kernel timing for benchmarks: while enabled, hist_fill records HIP events on
+ * its stream around the fill kernel and around the merge-reduction kernel.
+ * Enabling (or disabling) clears what was recorded. */
+HIST_API hist_status hist_timing(hist_t *h, int enable);
+
+/* Sums of the recorded fill-kernel and merge-kernel durations (ms) and the
+ * number of fill launches since the last read or hist_timing call; clears
+ * them.  Waits for the recorded events. */
+HIST_API hist_status hist_timing_read(hist_t *h, double *fill_ms, double *merge_ms,
+                                      int64_t *launches);
+
+/* ---- batched filling ------------------------------------------------------- */
+
+/* One member of a batch: coordinates/weights as for hist_fill. */
+typedef struct {
+    const void *coords[3];   /* DEVICE pointers, first dims used */
+    const void *weights;     /* DEVICE pointer or NULL */
+    int64_t n;
+    hist_dtype dtype;
+} hist_fill_desc;
+
+/* Builds a batch over k handles (distinct, all on this device): a tile list
+ * over every member's events and a per-member plan, uploaded once, and a HIP
+ * graph that holds one persistent fill launch for all members.  The inputs
+ * named in descs are bound into the graph: every hist_batch_launch reads the
+ * same device buffers.  Synchronizes.  Errors: HIST_EINVAL, HIST_ENOMEM. */
+HIST_API hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fill_desc *descs,
+                              hist_batch_t **out, void *stream);
+
+/* Replays the batch graph on `stream`: fills every member once (adding to its
+ * sums, Sec. 3.3).  Asynchronous. */
+HIST_API hist_status hist_batch_launch(hist_batch_t *b, void *stream);
+
+/* Same work as one replay, launched directly without the graph. */
+HIST_API hist_status hist_batch_launch_eager(hist_batch_t *b, void *stream);
+
+HIST_API hist_status hist_batch_destroy(hist_batch_t *b);
+
+/* ---- introspection -------------------------------------------------------- */
+
+HIST_API int64_t hist_nbins_total(const hist_t *h);   /* T, or -1 for NULL */
+HIST_API int hist_nstats(const hist_t *h);             /* S, or -1 for NULL */
+HIST_API const char *hist_strerror(hist_status s);
+HIST_API const char *hist_last_error(void);          /* thread-local, never NULL */
+HIST_API const char *hist_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HIST_H */

@@ -1,0 +1,721 @@
+// fill.hip -- histogram fill kernels for gfx950 (MI355X).
+//
+// One pass over a bulk of events does the three Fill steps of arXiv:2401.13310
+// Sec. 3.1 together: find the bin on every axis, add the weight (and its
+// square) to that bin, and add the event's terms to the statistics sums of
+// Sec. 3.2.  Like the paper's two-stage kernel (Sec. 3.2), each workgroup
+// first accumulates into a private copy of (a window of) the histogram in LDS
+// and merges it into the global histogram at the end; the statistics are
+// reduced in the same pass instead of by separate reduction kernels.
+//
+// gfx950 specifics that shape the code:
+//   - 160 KB of LDS per workgroup: one workgroup per CU can privatize 80K
+//     16-bit counters, 40K 32-bit counters or 10K binary64 (sum, sum2) pairs;
+//   - scattered global atomics are two orders of magnitude slower than LDS
+//     atomics, so they are only a fallback for bins outside the LDS window,
+//     and large windows merge through a staging buffer and a reduction kernel
+//     instead of coalesced atomics;
+//   - small histograms keep up to 64 interleaved copies so the 64 lanes of a
+//     wave that hit the same bin update different LDS words (no serialized
+//     same-address atomics).
+#include "kernels.h"
+
+#include <mutex>
+#include <unordered_set>
+
+namespace hg {
+
+template <int D>
+struct NStats {
+    static constexpr int v = 2 + 2 * D + D * (D - 1) / 2;
+};
+
+__device__ __forceinline__ void lds_add_u32(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add_f64(double *p, double v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ float lds_add_rtn_f32(float *p, float v)
+{
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add_f32(float *p, float v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void gl_add_u64(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gl_add_f64(double *p, double v)
+{
+    unsafeAtomicAdd(p, v);
+}
+
+// Exact rounding error of fl(a + b) (Knuth's TwoSum).  The sum is formed here,
+// with contraction off, so it is the same rounded value the LDS atomic stored
+// (a product feeding b must not be fused into it).
+__device__ __forceinline__ float two_sum_err(float a, float b)
+{
+#pragma clang fp contract(off)
+    float s = a + b;
+    float bp = s - a;
+    float ap = s - bp;
+    return (a - ap) + (b - bp);
+}
+
+// Per-event statistics terms, rounded in the order w, w*w, w*x, (w*x)*x,
+// (w*x_c)*x_a -- the same products the reference definition forms.
+template <int D>
+__device__ __forceinline__ void stats_add(double (&st)[NStats<D>::v], const double (&x)[D],
+                                          double w)
+{
+#pragma clang fp contract(off)
+    st[0] += w;
+    st[1] += w * w;
+    int k = 2;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const double wx = w * x[a];
+        st[k++] += wx;
+        st[k++] += wx * x[a];
+#pragma unroll
+        for (int c = 0; c < a; ++c)
+            st[k++] += (w * x[c]) * x[a];
+    }
+}
+
+// Block reduction of the statistics partials, then one binary64 atomic per
+// statistic per workgroup (sums accumulate across fills).
+template <int NS>
+__device__ __forceinline__ void reduce_stats(double (&st)[NS], double *red, double *out)
+{
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = threadIdx.x / kWave;
+    const int nw = blockDim.x / kWave;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double v = st[k];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1)
+            v += __shfl_xor(v, off, kWave);
+        st[k] = v;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k)
+            red[wave * NS + k] = st[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < NS) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w)
+            s += red[w * NS + threadIdx.x];
+        if (s != 0.0)
+            gl_add_f64(&out[threadIdx.x], s);
+    }
+}
+
+template <int D>
+__device__ __forceinline__ void stage_models(const AxisDev (&ax)[kMaxDims], char *smem)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (ax[a].kind == AX_LEARNED && ax[a].lds_model >= 0) {
+            const double *src = reinterpret_cast<const double *>(ax[a].model);
+            double *dst = reinterpret_cast<double *>(smem + ax[a].lds_model);
+            const int nd = ax[a].nseg * (int)(sizeof(ModelSeg) / sizeof(double));
+            for (int i = threadIdx.x; i < nd; i += blockDim.x)
+                dst[i] = src[i];
+        }
+    }
+}
+
+// 32-bit words of the LDS window arrays.
+__device__ __forceinline__ int window_words(int acc, int win_len, int copies)
+{
+    if (acc == ACC_U32)
+        return win_len * copies;
+    if (acc == ACC_U16)
+        return (win_len + 1) >> 1;
+    return win_len * copies * 4;   // F64: 2 doubles, F32C: 4 floats per bin and copy
+}
+
+// Moves the high nibble of every 16-bit counter to the global counts, so each
+// counter is left <= 0x0FFF and can take kU16EpochEvents more increments.
+__device__ __forceinline__ void drain_u16(uint32_t *win, int words, int32_t win_lo, uint64_t *cnt)
+{
+    for (int i = threadIdx.x; i < words; i += blockDim.x) {
+        const uint32_t v = win[i];
+        const uint32_t m = v & 0xF000F000u;
+        if (m) {
+            win[i] = v - m;
+            const int64_t g0 = (int64_t)win_lo + 2 * (int64_t)i;
+            if (m & 0xFFFFu)
+                gl_add_u64(&cnt[g0], m & 0xFFFFu);
+            if (m >> 16)
+                gl_add_u64(&cnt[g0 + 1], m >> 16);
+        }
+    }
+}
+
+// LDS window -> global histogram (atomics) or -> this block's staging slot.
+template <int ACC>
+__device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A)
+{
+    const int W = A.win_len;
+    const int C = A.copies;
+    if (ACC == ACC_U32) {
+        if (A.merge == MERGE_STAGE) {
+            uint32_t *st = static_cast<uint32_t *>(A.stage) + (int64_t)blockIdx.x * A.stage_stride;
+            for (int l = threadIdx.x; l < W; l += blockDim.x) {
+                uint32_t c = 0;
+                for (int r = 0; r < C; ++r)
+                    c += win[l * C + r];
+                st[l] = c;
+            }
+        } else {
+            for (int l = threadIdx.x; l < W; l += blockDim.x) {
+                uint32_t c = 0;
+                for (int r = 0; r < C; ++r)
+                    c += win[l * C + r];
+                if (c)
+                    gl_add_u64(&A.cnt[A.win_lo + l], c);
+            }
+        }
+    } else if (ACC == ACC_U16) {
+        const int words = (W + 1) >> 1;
+        if (A.merge == MERGE_STAGE) {
+            uint32_t *st = static_cast<uint32_t *>(A.stage) + (int64_t)blockIdx.x * A.stage_stride;
+            for (int i = threadIdx.x; i < words; i += blockDim.x)
+                st[i] = win[i];
+        } else {
+            for (int i = threadIdx.x; i < words; i += blockDim.x) {
+                const uint32_t v = win[i];
+                const int64_t g0 = (int64_t)A.win_lo + 2 * (int64_t)i;
+                if (v & 0xFFFFu)
+                    gl_add_u64(&A.cnt[g0], v & 0xFFFFu);
+                if (v >> 16)
+                    gl_add_u64(&A.cnt[g0 + 1], v >> 16);
+            }
+        }
+    } else {
+        // F64: [sumw][sumw2] each W*C doubles; F32C: [sw][cw][sw2][cw2] each W*C floats
+        const int n1 = W * C;
+        for (int l = threadIdx.x; l < W; l += blockDim.x) {
+            double s = 0.0, s2 = 0.0;
+            if (ACC == ACC_F64) {
+                const double *d = reinterpret_cast<const double *>(win);
+                for (int r = 0; r < C; ++r) {
+                    s += d[l * C + r];
+                    s2 += d[n1 + l * C + r];
+                }
+            } else {
+                const float *f = reinterpret_cast<const float *>(win);
+                for (int r = 0; r < C; ++r) {
+                    s += (double)f[l * C + r] + (double)f[n1 + l * C + r];
+                    s2 += (double)f[2 * n1 + l * C + r] + (double)f[3 * n1 + l * C + r];
+                }
+            }
+            if (A.merge == MERGE_STAGE) {
+                double *st = static_cast<double *>(A.stage) + (int64_t)blockIdx.x * 2 * A.stage_stride;
+                st[l] = s;
+                st[A.stage_stride + l] = s2;
+            } else if (s != 0.0 || s2 != 0.0) {
+                gl_add_f64(&A.sumw[A.win_lo + l], s);
+                gl_add_f64(&A.sumw2[A.win_lo + l], s2);
+            }
+        }
+    }
+}
+
+template <int D, typename T, int ACC, bool W, int U>
+__global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    constexpr int NS = NStats<D>::v;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+
+    stage_models<D>(A.ax, smem);
+    uint32_t *win = reinterpret_cast<uint32_t *>(smem + A.lds_win);
+    const int words = window_words(ACC, A.win_len, A.copies);
+    for (int i = tid; i < words; i += nthr)
+        win[i] = 0u;
+    __syncthreads();
+
+    double st[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        st[k] = 0.0;
+
+    const int64_t start = (int64_t)blockIdx.x * A.per_block;
+    const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
+    const int cp = (ACC == ACC_U16) ? 0 : tid % A.copies;
+    const uint32_t wlen = (uint32_t)A.win_len;
+    int it = 0;
+
+    for (int64_t base = start; base < end; base += (int64_t)nthr * U) {
+        T xv[U][D];
+        T wv[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t i = base + (int64_t)j * nthr + tid;
+            const bool ok = i < end;
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                xv[j][a] = ok ? static_cast<const T *>(A.coords[a])[i] : T(0);
+            if (W)
+                wv[j] = ok ? static_cast<const T *>(A.w)[i] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t i = base + (int64_t)j * nthr + tid;
+            if (i < end) {
+                double x[D];
+                int32_t g = 0;
+                bool inside = true;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    x[a] = (double)xv[j][a];
+                    const int32_t b = axis_bin(x[a], A.ax[a], smem);
+                    inside = inside && (uint32_t)(b - 1) < (uint32_t)A.ax[a].nbins;
+                    g += (a == 0) ? b : b * A.ax[a].stride;
+                }
+                const double w = W ? (double)wv[j] : 1.0;
+                if (inside)
+                    stats_add<D>(st, x, w);
+                const uint32_t l = (uint32_t)(g - A.win_lo);
+                if (l < wlen) {
+                    if (ACC == ACC_U32) {
+                        lds_add_u32(&win[l * A.copies + cp], 1u);
+                    } else if (ACC == ACC_U16) {
+                        lds_add_u32(&win[l >> 1], 1u << ((l & 1u) << 4));
+                    } else if (ACC == ACC_F64) {
+                        double *s = reinterpret_cast<double *>(win);
+                        const uint32_t idx = l * A.copies + cp;
+                        lds_add_f64(&s[idx], w);
+                        lds_add_f64(&s[wlen * A.copies + idx], w * w);
+                    } else {
+                        float *s = reinterpret_cast<float *>(win);
+                        const uint32_t n1 = wlen * A.copies;
+                        const uint32_t idx = l * A.copies + cp;
+                        const float wf = (float)wv[j];
+                        const float w2 = wf * wf;
+                        const float e2 = __builtin_fmaf(wf, wf, -w2);   // exact: wf*wf = w2 + e2
+                        const float o1 = lds_add_rtn_f32(&s[idx], wf);
+                        const float c1 = two_sum_err(o1, wf);
+                        const float o2 = lds_add_rtn_f32(&s[2 * n1 + idx], w2);
+                        const float c2 = two_sum_err(o2, w2) + e2;
+                        lds_add_f32(&s[n1 + idx], c1);
+                        lds_add_f32(&s[3 * n1 + idx], c2);
+                    }
+                } else if (W) {
+                    gl_add_f64(&A.sumw[g], w);
+                    gl_add_f64(&A.sumw2[g], w * w);
+                } else {
+                    gl_add_u64(&A.cnt[g], 1ull);
+                }
+            }
+        }
+        if (ACC == ACC_U16 && ++it == A.epoch_iters) {
+            it = 0;
+            __syncthreads();
+            drain_u16(win, words, A.win_lo, A.cnt);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    reduce_stats<NS>(st, reinterpret_cast<double *>(smem), A.stats);
+    merge_window<ACC>(win, A);
+}
+
+// Sums the staging slots of `nblocks` fill workgroups into the histogram.
+// blockIdx.y selects a group of slots; groups add with coalesced atomics.
+template <int ACC>
+__global__ void __launch_bounds__(256) stage_reduce_kernel(const FillArgs A, int nblocks,
+                                                           int per_group)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int b0 = blockIdx.y * per_group;
+    const int b1 = b0 + per_group < nblocks ? b0 + per_group : nblocks;
+    const int W = A.win_len;
+    if (ACC == ACC_U32) {
+        if (u >= W)
+            return;
+        const uint32_t *st = static_cast<const uint32_t *>(A.stage);
+        uint64_t s = 0;
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b)
+            s += st[(int64_t)b * A.stage_stride + u];
+        if (s)
+            gl_add_u64(&A.cnt[A.win_lo + u], s);
+    } else if (ACC == ACC_U16) {
+        const int words = (W + 1) >> 1;
+        if (u >= words)
+            return;
+        const uint32_t *st = static_cast<const uint32_t *>(A.stage);
+        uint64_t lo = 0, hi = 0;
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) {
+            const uint32_t v = st[(int64_t)b * A.stage_stride + u];
+            lo += v & 0xFFFFu;
+            hi += v >> 16;
+        }
+        const int64_t g0 = (int64_t)A.win_lo + 2 * u;
+        if (lo)
+            gl_add_u64(&A.cnt[g0], lo);
+        if (hi)
+            gl_add_u64(&A.cnt[g0 + 1], hi);
+    } else {
+        if (u >= W)
+            return;
+        const double *st = static_cast<const double *>(A.stage);
+        double s = 0.0, s2 = 0.0;
+#pragma unroll 8
+        for (int b = b0; b < b1; ++b) {
+            s += st[(int64_t)b * 2 * A.stage_stride + u];
+            s2 += st[(int64_t)b * 2 * A.stage_stride + A.stage_stride + u];
+        }
+        if (s != 0.0 || s2 != 0.0) {
+            gl_add_f64(&A.sumw[A.win_lo + u], s);
+            gl_add_f64(&A.sumw2[A.win_lo + u], s2);
+        }
+    }
+}
+
+// Find bin only: the global bin of every event (grid-stride).
+template <int D, typename T>
+__global__ void __launch_bounds__(kMaxThreads) findbin_kernel(const FillArgs A, int32_t *out)
+{
+    extern __shared__ __align__(16) char smem[];
+    stage_models<D>(A.ax, smem);
+    __syncthreads();
+    const int64_t stride = (int64_t)blockDim.x * gridDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride) {
+        int32_t g = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double x = (double)static_cast<const T *>(A.coords[a])[i];
+            const int32_t b = axis_bin(x, A.ax[a], smem);
+            g += (a == 0) ? b : b * A.ax[a].stride;
+        }
+        out[i] = g;
+    }
+}
+
+// Tiled strategy, pass 1: global bin of every event into A.gbins, with the
+// statistics reduced in the same pass.
+template <int D, typename T, bool W>
+__global__ void __launch_bounds__(kMaxThreads) tiled_bins_kernel(const FillArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    constexpr int NS = NStats<D>::v;
+    stage_models<D>(A.ax, smem);
+    __syncthreads();
+    double st[NS];
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+        st[k] = 0.0;
+    const int64_t stride = (int64_t)blockDim.x * gridDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride) {
+        double x[D];
+        int32_t g = 0;
+        bool inside = true;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            x[a] = (double)static_cast<const T *>(A.coords[a])[i];
+            const int32_t b = axis_bin(x[a], A.ax[a], smem);
+            inside = inside && (uint32_t)(b - 1) < (uint32_t)A.ax[a].nbins;
+            g += (a == 0) ? b : b * A.ax[a].stride;
+        }
+        A.gbins[i] = g;
+        if (inside)
+            stats_add<D>(st, x, W ? (double)static_cast<const T *>(A.w)[i] : 1.0);
+    }
+    __syncthreads();
+    reduce_stats<NS>(st, reinterpret_cast<double *>(smem), A.stats);
+}
+
+// Tiled strategy, pass 2: block (x, y) accumulates the events of chunk x whose
+// bin falls in tile y (bins [y*tile_len, (y+1)*tile_len)) in LDS, then merges.
+template <int ACC, typename T, bool W>
+__global__ void __launch_bounds__(kMaxThreads) tile_kernel(const TileArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int32_t t0 = blockIdx.y * A.tile_len;
+    const int32_t tlen = (A.T - t0) < A.tile_len ? (A.T - t0) : A.tile_len;
+    uint32_t *win = reinterpret_cast<uint32_t *>(smem + A.lds_win);
+    const int words = window_words(ACC, tlen, A.copies);
+    for (int i = tid; i < words; i += nthr)
+        win[i] = 0u;
+    __syncthreads();
+    const int64_t start = (int64_t)blockIdx.x * A.per_block;
+    const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
+    const int cp = (ACC == ACC_U16) ? 0 : tid % A.copies;
+    int it = 0;
+    constexpr int U = kTileUnroll;
+    for (int64_t base = start; base < end; base += (int64_t)nthr * U) {
+        int32_t gv[U];
+        T wv[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int64_t i = base + (int64_t)j * nthr + tid;
+            const bool ok = i < end;
+            gv[j] = ok ? A.gbins[i] : -1;
+            if (W)
+                wv[j] = ok ? static_cast<const T *>(A.w)[i] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t l = (uint32_t)(gv[j] - t0);
+            if (gv[j] >= 0 && l < (uint32_t)tlen) {
+                if (ACC == ACC_U32) {
+                    lds_add_u32(&win[l * A.copies + cp], 1u);
+                } else if (ACC == ACC_U16) {
+                    lds_add_u32(&win[l >> 1], 1u << ((l & 1u) << 4));
+                } else {
+                    const double w = (double)wv[j];
+                    double *s = reinterpret_cast<double *>(win);
+                    const uint32_t idx = l * A.copies + cp;
+                    lds_add_f64(&s[idx], w);
+                    lds_add_f64(&s[(uint32_t)tlen * A.copies + idx], w * w);
+                }
+            }
+        }
+        if (ACC == ACC_U16 && ++it == A.epoch_iters) {
+            it = 0;
+            __syncthreads();
+            drain_u16(win, words, t0, A.cnt);
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (ACC == ACC_U32) {
+        for (int l = tid; l < tlen; l += nthr) {
+            uint32_t c = 0;
+            for (int r = 0; r < A.copies; ++r)
+                c += win[l * A.copies + r];
+            if (c)
+                gl_add_u64(&A.cnt[t0 + l], c);
+        }
+    } else if (ACC == ACC_U16) {
+        for (int i = tid; i < words; i += nthr) {
+            const uint32_t v = win[i];
+            const int64_t g0 = (int64_t)t0 + 2 * (int64_t)i;
+            if (v & 0xFFFFu)
+                gl_add_u64(&A.cnt[g0], v & 0xFFFFu);
+            if (v >> 16)
+                gl_add_u64(&A.cnt[g0 + 1], v >> 16);
+        }
+    } else {
+        const double *d = reinterpret_cast<const double *>(win);
+        const int n1 = tlen * A.copies;
+        for (int l = tid; l < tlen; l += nthr) {
+            double s = 0.0, s2 = 0.0;
+            for (int r = 0; r < A.copies; ++r) {
+                s += d[l * A.copies + r];
+                s2 += d[n1 + l * A.copies + r];
+            }
+            if (s != 0.0 || s2 != 0.0) {
+                gl_add_f64(&A.sumw[t0 + l], s);
+                gl_add_f64(&A.sumw2[t0 + l], s2);
+            }
+        }
+    }
+}
+
+__global__ void zero_u64_kernel(uint64_t *p, int64_t n)
+{
+    const int64_t stride = (int64_t)blockDim.x * gridDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = 0ull;
+}
+__global__ void zero_f64_kernel(double *p, int64_t n)
+{
+    const int64_t stride = (int64_t)blockDim.x * gridDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        p[i] = 0.0;
+}
+__global__ void add_u64_to_f64_kernel(double *dst, const uint64_t *src, int64_t n)
+{
+    const int64_t stride = (int64_t)blockDim.x * gridDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        dst[i] += (double)src[i];
+}
+
+// ------------------------------------------------------------------ launchers
+
+// Lets a kernel take the whole 160 KB of gfx950 LDS (once per kernel).
+template <typename K>
+static void allow_big_lds(K kernel)
+{
+    static std::mutex mu;
+    static std::unordered_set<const void *> done;
+    const void *key = reinterpret_cast<const void *>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.insert(key).second)
+        (void)hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
+}
+
+template <int D, typename T, int ACC, bool W>
+static hipError_t launch_fill_t(int threads, int blocks, size_t lds, const FillArgs &a,
+                                hipStream_t s)
+{
+    auto k = fill_kernel<D, T, ACC, W, fill_unroll(D, sizeof(T) == 4)>;
+    allow_big_lds(k);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int D, typename T>
+static hipError_t launch_fill_d(int acc, bool weighted, int threads, int blocks, size_t lds,
+                                const FillArgs &a, hipStream_t s)
+{
+    if (!weighted) {
+        if (acc == ACC_U32)
+            return launch_fill_t<D, T, ACC_U32, false>(threads, blocks, lds, a, s);
+        if (acc == ACC_U16)
+            return launch_fill_t<D, T, ACC_U16, false>(threads, blocks, lds, a, s);
+        return hipErrorInvalidValue;
+    }
+    if (acc == ACC_F64)
+        return launch_fill_t<D, T, ACC_F64, true>(threads, blocks, lds, a, s);
+    if constexpr (sizeof(T) == 4) {
+        if (acc == ACC_F32C)
+            return launch_fill_t<D, T, ACC_F32C, true>(threads, blocks, lds, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_fill(int dims, bool f32, int acc, bool weighted, int threads, int blocks,
+                       size_t lds, const FillArgs &a, hipStream_t s)
+{
+    switch (dims * 2 + (f32 ? 1 : 0)) {
+    case 2: return launch_fill_d<1, double>(acc, weighted, threads, blocks, lds, a, s);
+    case 3: return launch_fill_d<1, float>(acc, weighted, threads, blocks, lds, a, s);
+    case 4: return launch_fill_d<2, double>(acc, weighted, threads, blocks, lds, a, s);
+    case 5: return launch_fill_d<2, float>(acc, weighted, threads, blocks, lds, a, s);
+    case 6: return launch_fill_d<3, double>(acc, weighted, threads, blocks, lds, a, s);
+    case 7: return launch_fill_d<3, float>(acc, weighted, threads, blocks, lds, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stage_reduce(int acc, int blocks_used, const FillArgs &a, hipStream_t s)
+{
+    const int units = acc == ACC_U16 ? (a.win_len + 1) / 2 : a.win_len;
+    const int per_group = 32;
+    const int groups = (blocks_used + per_group - 1) / per_group;
+    dim3 grid((units + 255) / 256, groups);
+    switch (acc) {
+    case ACC_U32: hipLaunchKernelGGL(stage_reduce_kernel<ACC_U32>, grid, dim3(256), 0, s, a, blocks_used, per_group); break;
+    case ACC_U16: hipLaunchKernelGGL(stage_reduce_kernel<ACC_U16>, grid, dim3(256), 0, s, a, blocks_used, per_group); break;
+    default: hipLaunchKernelGGL(stage_reduce_kernel<ACC_F64>, grid, dim3(256), 0, s, a, blocks_used, per_group); break;
+    }
+    return hipGetLastError();
+}
+
+template <int D, typename T>
+static hipError_t launch_findbin_t(int threads, int blocks, size_t lds, const FillArgs &a,
+                                   int32_t *out, hipStream_t s)
+{
+    auto k = findbin_kernel<D, T>;
+    allow_big_lds(k);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_findbin(int dims, bool f32, int threads, int blocks, size_t lds,
+                          const FillArgs &a, int32_t *out, hipStream_t s)
+{
+    switch (dims * 2 + (f32 ? 1 : 0)) {
+    case 2: return launch_findbin_t<1, double>(threads, blocks, lds, a, out, s);
+    case 3: return launch_findbin_t<1, float>(threads, blocks, lds, a, out, s);
+    case 4: return launch_findbin_t<2, double>(threads, blocks, lds, a, out, s);
+    case 5: return launch_findbin_t<2, float>(threads, blocks, lds, a, out, s);
+    case 6: return launch_findbin_t<3, double>(threads, blocks, lds, a, out, s);
+    case 7: return launch_findbin_t<3, float>(threads, blocks, lds, a, out, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int D, typename T, bool W>
+static hipError_t launch_tb_t(int threads, int blocks, size_t lds, const FillArgs &a, hipStream_t s)
+{
+    auto k = tiled_bins_kernel<D, T, W>;
+    allow_big_lds(k);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiled_bins(int dims, bool f32, bool weighted, int threads, int blocks,
+                             size_t lds, const FillArgs &a, hipStream_t s)
+{
+    const int key = (dims * 2 + (f32 ? 1 : 0)) * 2 + (weighted ? 1 : 0);
+    switch (key) {
+    case 4: return launch_tb_t<1, double, false>(threads, blocks, lds, a, s);
+    case 5: return launch_tb_t<1, double, true>(threads, blocks, lds, a, s);
+    case 6: return launch_tb_t<1, float, false>(threads, blocks, lds, a, s);
+    case 7: return launch_tb_t<1, float, true>(threads, blocks, lds, a, s);
+    case 8: return launch_tb_t<2, double, false>(threads, blocks, lds, a, s);
+    case 9: return launch_tb_t<2, double, true>(threads, blocks, lds, a, s);
+    case 10: return launch_tb_t<2, float, false>(threads, blocks, lds, a, s);
+    case 11: return launch_tb_t<2, float, true>(threads, blocks, lds, a, s);
+    case 12: return launch_tb_t<3, double, false>(threads, blocks, lds, a, s);
+    case 13: return launch_tb_t<3, double, true>(threads, blocks, lds, a, s);
+    case 14: return launch_tb_t<3, float, false>(threads, blocks, lds, a, s);
+    case 15: return launch_tb_t<3, float, true>(threads, blocks, lds, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int ACC, typename T, bool W>
+static hipError_t launch_tile_t(int threads, int bx, int tiles, size_t lds, const TileArgs &t,
+                                hipStream_t s)
+{
+    auto k = tile_kernel<ACC, T, W>;
+    allow_big_lds(k);
+    hipLaunchKernelGGL(k, dim3(bx, tiles), dim3(threads), lds, s, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile(int acc, bool f32, int threads, int blocks_x, int tiles, size_t lds,
+                       const TileArgs &t, hipStream_t s)
+{
+    if (acc == ACC_U32)
+        return launch_tile_t<ACC_U32, double, false>(threads, blocks_x, tiles, lds, t, s);
+    if (acc == ACC_U16)
+        return launch_tile_t<ACC_U16, double, false>(threads, blocks_x, tiles, lds, t, s);
+    if (f32)
+        return launch_tile_t<ACC_F64, float, true>(threads, blocks_x, tiles, lds, t, s);
+    return launch_tile_t<ACC_F64, double, true>(threads, blocks_x, tiles, lds, t, s);
+}
+
+static int grid_for(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (int)(b < 4096 ? (b < 1 ? 1 : b) : 4096);
+}
+
+hipError_t launch_zero_u64(uint64_t *p, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+hipError_t launch_add_u64_to_f64(double *dst, const uint64_t *src, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(add_u64_to_f64_kernel, dim3(grid_for(n)), dim3(256), 0, s, dst, src, n);
+    return hipGetLastError();
+}
+
+}  // namespace hg

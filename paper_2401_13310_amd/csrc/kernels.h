@@ -1,0 +1,90 @@
+// kernels.h -- launch interface between the host library and the gfx950
+// kernels of the histogram library.
+#pragma once
+
+#include "hist_internal.h"
+
+namespace hg {
+
+// LDS accumulators for the window of bins a block privatizes.
+enum Acc : int32_t {
+    ACC_U32 = 0,   // unit weights: 32-bit counters, `copies` interleaved copies
+    ACC_U16 = 1,   // unit weights: 16-bit counters packed in pairs, drained by
+                   // periodic scans so they provably never overflow
+    ACC_F64 = 2,   // weights: binary64 sum and sum of squares, `copies` copies
+    ACC_F32C = 3   // FP32 weights: FP32 sums with TwoSum compensation terms
+};
+
+enum Merge : int32_t { MERGE_ATOMIC = 0, MERGE_STAGE = 1 };
+
+// Bytes one bin needs in LDS for one copy.
+__host__ __device__ inline int acc_bytes(int acc)
+{
+    return acc == ACC_U32 ? 4 : acc == ACC_U16 ? 2 : 16;
+}
+
+// Largest number of events one block may add between two drains of the
+// 16-bit counters: a drain leaves every counter <= 0x0FFF, so 61440 more
+// increments reach at most 0xFFFF.
+constexpr int kU16EpochEvents = 61440;
+constexpr int kRedBytes = 16 * kMaxStats * 8;      // per-wave statistics partials
+constexpr int kMaxThreads = 1024;
+constexpr int kTileUnroll = 4;
+
+// Events each thread loads per loop iteration of the fill kernel.
+__host__ __device__ constexpr int fill_unroll(int D, bool f32) { return (D == 1 || f32) ? 8 : 4; }
+
+struct FillArgs {
+    AxisDev ax[kMaxDims];
+    const void *coords[kMaxDims];
+    const void *w;            // nullptr: unit weights
+    int64_t n;
+    int64_t per_block;        // events per block, multiple of threads * unroll
+    int32_t win_lo;           // first global bin held in LDS
+    int32_t win_len;          // bins held in LDS (0: every event uses global atomics)
+    int32_t copies;           // interleaved LDS copies (U32, F64, F32C)
+    int32_t merge;            // Merge
+    int32_t lds_win;          // byte offset of the window arrays in LDS
+    int32_t epoch_iters;      // U16: loop iterations between drains
+    uint64_t *cnt;            // [T] unit-weight counts
+    double *sumw, *sumw2;     // [T] weighted sums
+    double *stats;            // [S]
+    void *stage;              // staging, one slot of stage_stride units per block
+    int64_t stage_stride;     // units per block: u32 words (U32/U16) or bins (F64/F32C)
+    int32_t *gbins;           // TILED pass 1: global bin of every event
+};
+
+struct TileArgs {
+    const int32_t *gbins;
+    const void *w;            // nullptr: unit weights
+    int64_t n;
+    int64_t per_block;
+    int32_t tile_len;         // bins per tile
+    int32_t T;                // total bins
+    int32_t copies;
+    int32_t lds_win;
+    int32_t epoch_iters;
+    uint64_t *cnt;
+    double *sumw, *sumw2;
+};
+
+// Launchers (return the launch status).
+hipError_t launch_fill(int dims, bool f32, int acc, bool weighted, int threads, int blocks,
+                       size_t lds, const FillArgs &a, hipStream_t s);
+hipError_t launch_stage_reduce(int acc, int blocks_used, const FillArgs &a, hipStream_t s);
+hipError_t launch_findbin(int dims, bool f32, int threads, int blocks, size_t lds,
+                          const FillArgs &a, int32_t *out, hipStream_t s);
+hipError_t launch_tiled_bins(int dims, bool f32, bool weighted, int threads, int blocks,
+                             size_t lds, const FillArgs &a, hipStream_t s);
+hipError_t launch_tile(int acc, bool f32, int threads, int blocks_x, int tiles, size_t lds,
+                       const TileArgs &t, hipStream_t s);
+hipError_t launch_zero_u64(uint64_t *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
+hipError_t launch_add_u64_to_f64(double *dst, const uint64_t *src, int64_t n, hipStream_t s);
+
+// Learned index training (learned.hip).
+hipError_t launch_seg_of_edges(const AxisDev &ax, int32_t *seg, hipStream_t s);
+hipError_t launch_fit_segments(const AxisDev &ax, const int32_t *seg, ModelSeg *model,
+                               double *diag, hipStream_t s);
+
+}  // namespace hg

@@ -1,0 +1,99 @@
+// plan.h -- the histogram handle and the fill plans chosen for it.
+#pragma once
+
+#include "../../include/hist.h"
+#include "kernels.h"
+
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+namespace hg {
+
+constexpr int kMaxSegments = 512;
+
+// How one fill is launched.
+struct Plan {
+    int strategy = HIST_STRAT_LDS;   // hist_strategy (never AUTO here)
+    int acc = ACC_U32;               // Acc
+    int threads = 1024;
+    int blocks = 1;
+    int copies = 1;
+    int32_t win_lo = 0;              // LDS: first bin of the window
+    int32_t win_len = 0;             // LDS: window bins (0 = global only); TILED: tile bins
+    int merge = MERGE_ATOMIC;
+    int64_t per_block = 0;
+    int epoch_iters = 1;
+    int lds_base = 0;                // bytes before the window (statistics + models)
+    int lds = 0;                     // dynamic LDS bytes per workgroup
+};
+
+// Choices the autotuner (or a test) fixes for a shape; 0 / -1 mean "heuristic".
+struct PlanChoice {
+    int strategy = HIST_STRAT_AUTO;
+    int blocks = 0;          // total workgroups (x-dimension for tiles)
+    int blocks_per_cu = 0;
+    int copies = 0;
+    int merge = -1;
+    int64_t win_lo = -1;
+};
+
+}  // namespace hg
+
+struct hist_s {
+    int dims = 0;
+    uint32_t flags = 0;
+    int device = 0;
+    int64_t T = 0;
+    int S = 0;
+    int num_cu = 256;
+    int lds_max = 65536;
+    hg::AxisDev ax[hg::kMaxDims];
+    bool variable[hg::kMaxDims] = {false, false, false};
+    std::vector<double> edges_host[hg::kMaxDims];
+    double *d_edges[hg::kMaxDims] = {nullptr, nullptr, nullptr};
+    hg::ModelSeg *d_model[hg::kMaxDims] = {nullptr, nullptr, nullptr};
+    bool trained[hg::kMaxDims] = {false, false, false};
+    int index_feature[hg::kMaxDims] = {0, 0, 0};
+    double index_mean_window[hg::kMaxDims] = {0, 0, 0};
+    double index_max_window[hg::kMaxDims] = {0, 0, 0};
+    uint64_t *d_cnt = nullptr;
+    double *d_sumw = nullptr, *d_sumw2 = nullptr, *d_stats = nullptr;
+    void *d_stage = nullptr;
+    size_t stage_bytes = 0;
+    int32_t *d_gbins = nullptr;
+    int64_t gbins_cap = 0;
+    int64_t entries = 0;
+    hg::PlanChoice forced;                               // hist_set_strategy
+    // kernel timing (hist_timing): event pairs around the fill and merge kernels
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, int>> ev_fill, ev_merge;  // indices into ev_pool
+    int ev_next = 0;
+    std::map<std::tuple<int, int, int>, hg::PlanChoice> tuned;  // (acc, f32, n bucket)
+};
+
+namespace hg {
+
+hist_status set_error(hist_status st, const char *fmt, ...);
+uint64_t host_order_key(double x);
+hist_status zero_state(hist_s *h, hipStream_t s);
+hist_status ensure_stage(hist_s *h, size_t bytes, hipStream_t s);
+hist_status ensure_gbins(hist_s *h, int64_t count, hipStream_t s);
+FillArgs base_args(const hist_s *h, const void *const *coords, const void *w, int64_t n);
+// Places the learned models of the axes in LDS after the statistics area;
+// returns the first free LDS byte.
+int apply_model_offsets(const hist_s *h, FillArgs &a);
+Plan make_plan(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted);
+Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted,
+                      const PlanChoice &c);
+int timing_event(hist_s *h);
+hist_status run_plan(hist_s *h, const Plan &p, const void *const *coords, const void *w,
+                     int64_t n, hist_dtype dtype, hipStream_t s);
+size_t stage_bytes_for(const Plan &p);
+int64_t stage_stride_for(const Plan &p);
+int64_t tiled_chunk(const hist_s *h);
+int unroll_of(int dims, bool f32);
+
+}  // namespace hg

@@ -1,0 +1,452 @@
+// plan.hip -- choosing how a fill is launched, and the autotuner.
+//
+// A plan fixes the accumulation strategy (LDS window, global atomics, or bin
+// tiles), the LDS accumulator, the number of workgroups and LDS copies, the
+// window of bins held in LDS and the merge.  The heuristic picks from the
+// histogram shape and the gfx950 LDS budget; hist_tune replaces it with the
+// fastest candidate measured on a sample (the launch-shape sensitivity the
+// paper reports for its reductions in Sec. 4.3 is why the shape is measured
+// rather than fixed).
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+namespace hg {
+
+int unroll_of(int dims, bool f32) { return fill_unroll(dims, f32); }
+
+int apply_model_offsets(const hist_s *h, FillArgs &a)
+{
+    int off = kRedBytes;
+    for (int d = 0; d < h->dims; ++d) {
+        if (a.ax[d].kind == AX_LEARNED) {
+            a.ax[d].lds_model = off;
+            off += a.ax[d].nseg * (int)sizeof(ModelSeg);
+            off = (off + 15) & ~15;
+        } else {
+            a.ax[d].lds_model = -1;
+        }
+    }
+    return off;
+}
+
+size_t stage_bytes_for(const Plan &p)
+{
+    return (size_t)p.blocks * (size_t)stage_stride_for(p) *
+           (p.acc == ACC_U32 || p.acc == ACC_U16 ? 4 : 16);
+}
+
+int64_t stage_stride_for(const Plan &p)
+{
+    if (p.acc == ACC_U16)
+        return (p.win_len + 1) / 2;
+    return p.win_len;
+}
+
+int64_t tiled_chunk(const hist_s *h)
+{
+    (void)h;
+    return (int64_t)1 << 24;
+}
+
+static int window_bytes(int acc, int64_t len, int copies)
+{
+    if (acc == ACC_U16)
+        return (int)(((len + 1) / 2) * 4);
+    return (int)(len * copies * acc_bytes(acc));
+}
+
+Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted,
+                      const PlanChoice &c)
+{
+    Plan p;
+    const bool f32 = dtype == HIST_F32;
+    FillArgs probe;
+    std::memset(&probe, 0, sizeof(probe));
+    for (int d = 0; d < kMaxDims; ++d)
+        probe.ax[d] = h->ax[d];
+    const int base = apply_model_offsets(h, probe);
+    const int avail = h->lds_max - base;
+    p.lds_base = base;
+    p.threads = 1024;
+
+    int acc;
+    if (weighted)
+        acc = (f32 && (h->flags & HIST_F_ACC_F32C)) ? ACC_F32C : ACC_F64;
+    else
+        acc = (h->T * 4 <= avail) ? ACC_U32 : ACC_U16;
+    const int64_t cap = acc == ACC_U16 ? (int64_t)(avail / 4) * 2 : avail / acc_bytes(acc);
+
+    int strategy = c.strategy;
+    if (strategy == HIST_STRAT_AUTO) {
+        if (h->T <= cap) {
+            strategy = HIST_STRAT_LDS;
+        } else if (2 * cap >= h->T) {
+            strategy = HIST_STRAT_LDS;   // a window over most bins, the rest global
+        } else {
+            const int64_t tiles = (h->T + cap - 1) / cap;
+            strategy = tiles <= 16 ? HIST_STRAT_TILED : HIST_STRAT_GLOBAL;
+        }
+    }
+    p.strategy = strategy;
+
+    if (strategy == HIST_STRAT_GLOBAL) {
+        p.acc = weighted ? ACC_F64 : ACC_U32;
+        p.win_len = 0;
+        p.copies = 1;
+        p.merge = MERGE_ATOMIC;
+        p.lds = base;
+    } else if (strategy == HIST_STRAT_TILED) {
+        p.acc = weighted ? ACC_F64 : (h->T * 4 <= avail ? ACC_U32 : ACC_U16);
+        const int64_t tcap = p.acc == ACC_U16 ? (int64_t)(avail / 4) * 2 : avail / acc_bytes(p.acc);
+        p.win_len = (int32_t)std::min<int64_t>(tcap, h->T);
+        p.copies = 1;
+        p.merge = MERGE_ATOMIC;
+        p.lds = base + window_bytes(p.acc, p.win_len, 1);
+        p.epoch_iters = std::max(1, kU16EpochEvents / (p.threads * kTileUnroll));
+        const int64_t tiles = (h->T + p.win_len - 1) / p.win_len;
+        int bx = (int)std::max<int64_t>(1, (int64_t)h->num_cu * 2 / tiles);
+        if (c.blocks > 0)
+            bx = c.blocks;
+        p.blocks = bx;
+        return p;
+    } else {
+        p.acc = acc;
+        int64_t lo = 0, len = h->T;
+        if (h->T > cap) {
+            len = cap;
+            lo = c.win_lo >= 0 ? c.win_lo : 0;
+            if (lo + len > h->T)
+                lo = h->T - len;
+        }
+        p.win_lo = (int32_t)lo;
+        p.win_len = (int32_t)len;
+        int copies = 1;
+        if (acc != ACC_U16) {
+            if (c.copies > 0) {
+                copies = c.copies;
+            } else {
+                const int64_t fit = avail / std::max<int64_t>(1, len * acc_bytes(acc));
+                copies = (int)std::min<int64_t>(64, std::max<int64_t>(1, fit));
+            }
+            while (copies > 1 && window_bytes(acc, len, copies) > avail)
+                --copies;
+        }
+        p.copies = copies;
+        p.lds = base + window_bytes(acc, len, copies);
+    }
+
+    const int U = fill_unroll(h->dims, f32);
+    const int64_t step = (int64_t)p.threads * U;
+    int bpc = c.blocks_per_cu > 0 ? c.blocks_per_cu : (p.lds > h->lds_max / 2 ? 1 : 2);
+    if (p.lds * bpc > h->lds_max)
+        bpc = std::max(1, h->lds_max / std::max(1, p.lds));
+    int64_t G = c.blocks > 0 ? c.blocks : (int64_t)h->num_cu * bpc;
+    const int64_t need = (n + step - 1) / step;
+    if (G > need)
+        G = need;
+    if (G < 1)
+        G = 1;
+    int64_t per = (n + G - 1) / G;
+    per = (per + step - 1) / step * step;
+    G = (n + per - 1) / per;
+    if (G < 1)
+        G = 1;
+    p.blocks = (int)G;
+    p.per_block = per;
+    p.epoch_iters = std::max(1, kU16EpochEvents / (int)step);
+    if (p.strategy == HIST_STRAT_LDS) {
+        if (c.merge >= 0)
+            p.merge = c.merge;
+        else
+            p.merge = (double)G * window_bytes(p.acc, p.win_len, 1) > 8.0e6 ? MERGE_STAGE
+                                                                             : MERGE_ATOMIC;
+    }
+    return p;
+}
+
+// ------------------------------------------------------- tuned-plan cache --
+
+namespace {
+struct ShapeKey {
+    int dims;
+    int64_t T;
+    int kinds;
+    int weighted, f32;
+    uint32_t flags;
+    bool operator<(const ShapeKey &o) const
+    {
+        return std::tie(dims, T, kinds, weighted, f32, flags) <
+               std::tie(o.dims, o.T, o.kinds, o.weighted, o.f32, o.flags);
+    }
+};
+std::mutex g_cache_mu;
+std::map<ShapeKey, PlanChoice> g_cache;
+
+ShapeKey shape_key(const hist_s *h, bool weighted, bool f32)
+{
+    int kinds = 0;
+    for (int d = 0; d < h->dims; ++d)
+        kinds = kinds * 3 + h->ax[d].kind;
+    return ShapeKey{h->dims, h->T, kinds, weighted ? 1 : 0, f32 ? 1 : 0, h->flags};
+}
+}  // namespace
+
+Plan make_plan(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted)
+{
+    PlanChoice c = h->forced;
+    if (c.strategy == HIST_STRAT_AUTO) {
+        auto it = h->tuned.find(std::make_tuple(weighted ? 1 : 0, dtype == HIST_F32 ? 1 : 0, 0));
+        if (it != h->tuned.end()) {
+            c = it->second;
+        } else {
+            std::lock_guard<std::mutex> lock(g_cache_mu);
+            auto jt = g_cache.find(shape_key(h, weighted, dtype == HIST_F32));
+            if (jt != g_cache.end())
+                c = jt->second;
+        }
+    }
+    return plan_from_choice(h, n, dtype, weighted, c);
+}
+
+}  // namespace hg
+
+using namespace hg;
+
+extern "C" hist_status hist_set_strategy(hist_t *h, int strategy, int blocks, int subhists)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_set_strategy: NULL handle");
+    if (strategy < HIST_STRAT_AUTO || strategy > HIST_STRAT_TILED)
+        return set_error(HIST_EINVAL, "hist_set_strategy: unknown strategy %d", strategy);
+    if (blocks < 0 || subhists < 0 || subhists > 64)
+        return set_error(HIST_EINVAL, "hist_set_strategy: blocks >= 0, 0 <= subhists <= 64");
+    PlanChoice c;
+    c.strategy = strategy;
+    c.blocks = blocks;
+    c.copies = subhists;
+    c.merge = h->forced.merge;
+    c.win_lo = h->forced.win_lo;
+    h->forced = c;
+    return HIST_OK;
+}
+
+extern "C" hist_status hist_plan_info(hist_t *h, int64_t n, hist_dtype dtype, int weighted,
+                                      int *strategy, int *blocks, int *subhists,
+                                      int64_t *window_lo, int64_t *window_len, int *accumulator)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_plan_info: NULL handle");
+    if (n < 1)
+        n = 1;
+    Plan p = make_plan(h, n, dtype, weighted != 0);
+    if (strategy)
+        *strategy = p.strategy;
+    if (blocks)
+        *blocks = p.blocks;
+    if (subhists)
+        *subhists = p.copies;
+    if (window_lo)
+        *window_lo = p.win_lo;
+    if (window_len)
+        *window_len = p.win_len;
+    if (accumulator)
+        *accumulator = p.acc;
+    return HIST_OK;
+}
+
+// Extra control used by tests and the benchmark: merge mode (-1 auto) and LDS
+// window start (-1 auto) for later fills.
+extern "C" hist_status hist_set_window(hist_t *h, int64_t window_lo, int merge)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_set_window: NULL handle");
+    if (window_lo < -1 || window_lo >= h->T || merge < -1 || merge > MERGE_STAGE)
+        return set_error(HIST_EINVAL, "hist_set_window: bad window or merge");
+    h->forced.win_lo = window_lo;
+    h->forced.merge = merge;
+    return HIST_OK;
+}
+
+// ------------------------------------------------------------- autotuner --
+
+namespace {
+
+struct Saved {
+    uint64_t *cnt = nullptr;
+    double *sumw = nullptr, *sumw2 = nullptr, *stats = nullptr;
+    int64_t entries = 0;
+};
+
+hist_status save_state(hist_s *h, Saved &sv, hipStream_t s)
+{
+    const size_t T = (size_t)h->T;
+    if (hipMalloc(&sv.cnt, T * 8) != hipSuccess || hipMalloc(&sv.sumw, T * 8) != hipSuccess ||
+        hipMalloc(&sv.sumw2, T * 8) != hipSuccess || hipMalloc(&sv.stats, 8 * kMaxStats) != hipSuccess)
+        return set_error(HIST_ENOMEM, "hist_tune: cannot save the histogram");
+    if (hipMemcpyAsync(sv.cnt, h->d_cnt, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(sv.sumw, h->d_sumw, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(sv.sumw2, h->d_sumw2, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(sv.stats, h->d_stats, 8 * kMaxStats, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return set_error(HIST_EDEVICE, "hist_tune: save copy failed");
+    sv.entries = h->entries;
+    return HIST_OK;
+}
+
+hist_status restore_state(hist_s *h, Saved &sv, hipStream_t s)
+{
+    const size_t T = (size_t)h->T;
+    hist_status st = HIST_OK;
+    if (sv.cnt && (hipMemcpyAsync(h->d_cnt, sv.cnt, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                   hipMemcpyAsync(h->d_sumw, sv.sumw, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                   hipMemcpyAsync(h->d_sumw2, sv.sumw2, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+                   hipMemcpyAsync(h->d_stats, sv.stats, 8 * kMaxStats, hipMemcpyDeviceToDevice, s) != hipSuccess))
+        st = set_error(HIST_EDEVICE, "hist_tune: restore copy failed");
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(sv.cnt);
+    (void)hipFree(sv.sumw);
+    (void)hipFree(sv.sumw2);
+    (void)hipFree(sv.stats);
+    h->entries = sv.entries;
+    return st;
+}
+
+// Window of `len` bins with the largest sample mass.
+int64_t best_window(const std::vector<int32_t> &bins, int64_t T, int64_t len)
+{
+    std::vector<int64_t> cnt((size_t)T, 0);
+    for (int32_t g : bins)
+        if (g >= 0 && g < T)
+            cnt[(size_t)g]++;
+    int64_t run = 0;
+    for (int64_t g = 0; g < len && g < T; ++g)
+        run += cnt[(size_t)g];
+    int64_t best = run, at = 0;
+    for (int64_t g = len; g < T; ++g) {
+        run += cnt[(size_t)g] - cnt[(size_t)(g - len)];
+        if (run > best) {
+            best = run;
+            at = g - len + 1;
+        }
+    }
+    return at;
+}
+
+}  // namespace
+
+extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const void *weights,
+                                 int64_t n, hist_dtype dtype, void *stream)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_tune: NULL handle");
+    if (n <= 0 || !coords)
+        return set_error(HIST_EINVAL, "hist_tune: need a non-empty sample");
+    for (int d = 0; d < h->dims; ++d)
+        if (!coords[d])
+            return set_error(HIST_EINVAL, "hist_tune: coordinate %d is NULL", d);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return set_error(HIST_ECAPTURE, "hist_tune: stream is capturing");
+    const bool weighted = weights != nullptr;
+    const bool f32 = dtype == HIST_F32;
+
+    // window with the largest mass in the sample (only matters when T exceeds LDS)
+    PlanChoice auto_c;
+    Plan p0 = plan_from_choice(h, n, dtype, weighted, auto_c);
+    int64_t win_lo = 0;
+    const int64_t cap_len = p0.strategy == HIST_STRAT_LDS ? p0.win_len : 0;
+    if (cap_len > 0 && cap_len < h->T) {
+        int32_t *d_bins = nullptr;
+        if (hipMalloc(&d_bins, (size_t)n * 4) != hipSuccess)
+            return set_error(HIST_ENOMEM, "hist_tune: sample bins");
+        hist_status st = hist_findbin(h, coords, n, dtype, d_bins, stream);
+        std::vector<int32_t> bins((size_t)n);
+        if (st == HIST_OK &&
+            (hipMemcpyAsync(bins.data(), d_bins, (size_t)n * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+             hipStreamSynchronize(s) != hipSuccess))
+            st = set_error(HIST_EDEVICE, "hist_tune: sample bins copy");
+        (void)hipFree(d_bins);
+        if (st != HIST_OK)
+            return st;
+        win_lo = best_window(bins, h->T, cap_len);
+    }
+
+    // candidates
+    std::vector<PlanChoice> cands;
+    for (int strat : {HIST_STRAT_LDS, HIST_STRAT_GLOBAL, HIST_STRAT_TILED}) {
+        if (strat == HIST_STRAT_TILED && p0.acc != ACC_U16 && h->T * 16 <= h->lds_max)
+            continue;
+        if (strat == HIST_STRAT_LDS) {
+            for (int bpc : {1, 2}) {
+                for (int merge : {MERGE_ATOMIC, MERGE_STAGE}) {
+                    PlanChoice c;
+                    c.strategy = strat;
+                    c.blocks_per_cu = bpc;
+                    c.merge = merge;
+                    c.win_lo = win_lo;
+                    cands.push_back(c);
+                }
+            }
+        } else {
+            PlanChoice c;
+            c.strategy = strat;
+            cands.push_back(c);
+        }
+    }
+
+    Saved sv;
+    hist_status st = save_state(h, sv, s);
+    if (st != HIST_OK) {
+        restore_state(h, sv, s);
+        return st;
+    }
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    float best_ms = 1e30f;
+    PlanChoice best = cands.empty() ? auto_c : cands[0];
+    for (const PlanChoice &c : cands) {
+        Plan p = plan_from_choice(h, n, dtype, weighted, c);
+        if (p.strategy != c.strategy)
+            continue;
+        st = run_plan(h, p, coords, weights, n, dtype, s);   // warm-up (and allocations)
+        if (st != HIST_OK)
+            continue;
+        std::vector<float> ts;
+        for (int r = 0; r < 3; ++r) {
+            (void)hipEventRecord(e0, s);
+            st = run_plan(h, p, coords, weights, n, dtype, s);
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ts.push_back(ms);
+        }
+        std::sort(ts.begin(), ts.end());
+        if (st == HIST_OK && ts[1] < best_ms) {
+            best_ms = ts[1];
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    st = restore_state(h, sv, s);
+    h->tuned[std::make_tuple(weighted ? 1 : 0, f32 ? 1 : 0, 0)] = best;
+    {
+        std::lock_guard<std::mutex> lock(g_cache_mu);
+        g_cache[shape_key(h, weighted, f32)] = best;
+    }
+    if (std::getenv("HIST_LOG"))
+        fprintf(stderr, "hist_tune: T=%lld n=%lld -> strategy %d bpc %d merge %d win_lo %lld (%.3f ms)\n",
+                (long long)h->T, (long long)n, best.strategy, best.blocks_per_cu, best.merge,
+                (long long)best.win_lo, best_ms);
+    return st;
+}
