@@ -191,6 +191,10 @@ HIST_API hist_status hist_plan_info(hist_t *h, int64_t n, hist_dtype dtype, int 
  * by tests and benchmarks to pin a plan. */
 HIST_API hist_status hist_set_window(hist_t *h, int64_t window_lo, int merge);
 
+/* Fixes the threads per workgroup of later fills (0 = heuristic; 256, 512 or
+ * 1024).  Used by tests and benchmarks to pin a plan. */
+HIST_API hist_status hist_set_threads(hist_t *h, int threads);
+
 /* Kernel timing for benchmarks: while enabled, hist_fill records HIP events on
  * its stream around the fill kernel and around the merge-reduction kernel.
  * Enabling (or disabling) clears what was recorded. */

@@ -21,7 +21,7 @@ __all__ = [
     "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_findbin",
     "hist_stats", "hist_read", "hist_reset", "hist_train_index", "hist_set_search",
     "hist_index_info", "hist_set_strategy", "hist_set_window", "hist_tune", "hist_plan_info",
-    "hist_timing", "hist_timing_read",
+    "hist_timing", "hist_timing_read", "hist_set_threads",
     "hist_batch_create", "hist_batch_launch", "hist_batch_launch_eager", "hist_batch_destroy",
     "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_STRAT_AUTO",
     "HIST_STRAT_LDS", "HIST_STRAT_GLOBAL", "HIST_STRAT_TILED", "HIST_SEARCH_BINARY",
@@ -145,6 +145,10 @@ def hist_plan_info(h, n: int, dtype: int, weighted: bool) -> dict:
                                 ctypes.byref(ln), ctypes.byref(acc)), "hist_plan_info")
     return {"strategy": STRAT_NAMES[s.value], "blocks": b.value, "copies": c.value,
             "window_lo": lo.value, "window_len": ln.value, "accumulator": ACC_NAMES[acc.value]}
+
+
+def hist_set_threads(h, threads: int) -> None:
+    check(load().hist_set_threads(h, threads), "hist_set_threads")
 
 
 def hist_timing(h, enable: bool) -> None:
@@ -274,6 +278,9 @@ class Hist:
 
     def plan_info(self, n: int, dtype: int = HIST_F64, weighted: bool = False) -> dict:
         return hist_plan_info(self._h, n, dtype, weighted)
+
+    def set_threads(self, threads: int):
+        hist_set_threads(self._h, threads)
 
     def timing(self, enable: bool = True):
         hist_timing(self._h, enable)

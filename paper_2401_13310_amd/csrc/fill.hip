@@ -232,7 +232,97 @@ __device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A)
     }
 }
 
-template <int D, typename T, int ACC, bool W, int U>
+// Coalesced streaming loads of U events per thread: event base + j*blockDim +
+// tid of the block's range, addressed as 32-bit offsets from the block's
+// (wave-uniform) column pointers; CHECK predicates each load on the block's
+// length.  Non-temporal, so the event stream does not evict edges and models.
+template <int D, typename T, bool W, int U, bool CHECK>
+__device__ __forceinline__ void load_batch(const T *const (&xb)[D], const T *wb, uint32_t base,
+                                           uint32_t len, T (&x)[U][D], T (&w)[U])
+{
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const uint32_t i = base + (uint32_t)j * blockDim.x + threadIdx.x;
+        const bool ok = !CHECK || i < len;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            x[j][a] = ok ? __builtin_nontemporal_load(xb[a] + i) : T(0);
+        if (W)
+            w[j] = ok ? __builtin_nontemporal_load(wb + i) : T(0);
+        else
+            w[j] = T(0);
+    }
+}
+
+// Find bin, statistics and accumulation for the U loaded events of a thread
+// (events at offsets >= len are skipped).
+template <int D, typename T, int ACC, bool W, int U, int KS>
+__device__ __forceinline__ void process_batch(const FillArgs &A, const char *smem, uint32_t *win,
+                                              const T (&cx)[U][D], const T (&cw)[U],
+                                              uint32_t base, uint32_t len, int cp,
+                                              double (&st)[NStats<D>::v])
+{
+    const uint32_t wlen = (uint32_t)A.win_len;
+    double x[D][U];
+    int32_t b[D][U];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            x[a][j] = (double)cx[j][a];
+        axis_bins<U, kind_of_set<KS>()>(x[a], A.ax[a], smem, b[a]);
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        if (base + (uint32_t)j * blockDim.x + threadIdx.x >= len)
+            continue;
+        int32_t g = 0;
+        bool inside = true;
+        double xe[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            xe[a] = x[a][j];
+            inside = inside && (uint32_t)(b[a][j] - 1) < (uint32_t)A.ax[a].nbins;
+            g += (a == 0) ? b[a][j] : b[a][j] * A.ax[a].stride;
+        }
+        const double w = W ? (double)cw[j] : 1.0;
+        if (inside)
+            stats_add<D>(st, xe, w);
+        const uint32_t l = (uint32_t)(g - A.win_lo);
+        if (l < wlen) {
+            if (ACC == ACC_U32) {
+                lds_add_u32(&win[l * A.copies + cp], 1u);
+            } else if (ACC == ACC_U16) {
+                lds_add_u32(&win[l >> 1], 1u << ((l & 1u) << 4));
+            } else if (ACC == ACC_F64) {
+                double *s = reinterpret_cast<double *>(win);
+                const uint32_t idx = l * A.copies + cp;
+                lds_add_f64(&s[idx], w);
+                lds_add_f64(&s[wlen * A.copies + idx], w * w);
+            } else {
+                float *s = reinterpret_cast<float *>(win);
+                const uint32_t n1 = wlen * A.copies;
+                const uint32_t idx = l * A.copies + cp;
+                const float wf = (float)cw[j];
+                const float w2 = wf * wf;
+                const float e2 = __builtin_fmaf(wf, wf, -w2);   // exact: wf*wf = w2 + e2
+                const float o1 = lds_add_rtn_f32(&s[idx], wf);
+                const float c1 = two_sum_err(o1, wf);
+                const float o2 = lds_add_rtn_f32(&s[2 * n1 + idx], w2);
+                const float c2 = two_sum_err(o2, w2) + e2;
+                lds_add_f32(&s[n1 + idx], c1);
+                lds_add_f32(&s[3 * n1 + idx], c2);
+            }
+        } else if (W) {
+            gl_add_f64(&A.sumw[g], w);
+            gl_add_f64(&A.sumw2[g], w * w);
+        } else {
+            gl_add_u64(&A.cnt[g], 1ull);
+        }
+    }
+}
+
+template <int D, typename T, int ACC, bool W, int U, int KS>
 __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
 {
     extern __shared__ __align__(16) char smem[];
@@ -255,77 +345,43 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
     const int64_t start = (int64_t)blockIdx.x * A.per_block;
     const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
     const int cp = (ACC == ACC_U16) ? 0 : tid % A.copies;
-    const uint32_t wlen = (uint32_t)A.win_len;
     int it = 0;
 
-    for (int64_t base = start; base < end; base += (int64_t)nthr * U) {
-        T xv[U][D];
-        T wv[U];
+    // Software pipeline: the loads of the next U events per thread are in
+    // flight while the current ones are binned and accumulated.  Full
+    // iterations run without bounds checks; the last one is checked.
+    const uint32_t len = (uint32_t)(end > start ? end - start : 0);
+    const uint32_t step = (uint32_t)nthr * U;
+    const uint32_t nfull = len / step;
+    const T *xb[D];
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t i = base + (int64_t)j * nthr + tid;
-            const bool ok = i < end;
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-                xv[j][a] = ok ? static_cast<const T *>(A.coords[a])[i] : T(0);
-            if (W)
-                wv[j] = ok ? static_cast<const T *>(A.w)[i] : T(0);
-        }
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int64_t i = base + (int64_t)j * nthr + tid;
-            if (i < end) {
-                double x[D];
-                int32_t g = 0;
-                bool inside = true;
-#pragma unroll
-                for (int a = 0; a < D; ++a) {
-                    x[a] = (double)xv[j][a];
-                    const int32_t b = axis_bin(x[a], A.ax[a], smem);
-                    inside = inside && (uint32_t)(b - 1) < (uint32_t)A.ax[a].nbins;
-                    g += (a == 0) ? b : b * A.ax[a].stride;
-                }
-                const double w = W ? (double)wv[j] : 1.0;
-                if (inside)
-                    stats_add<D>(st, x, w);
-                const uint32_t l = (uint32_t)(g - A.win_lo);
-                if (l < wlen) {
-                    if (ACC == ACC_U32) {
-                        lds_add_u32(&win[l * A.copies + cp], 1u);
-                    } else if (ACC == ACC_U16) {
-                        lds_add_u32(&win[l >> 1], 1u << ((l & 1u) << 4));
-                    } else if (ACC == ACC_F64) {
-                        double *s = reinterpret_cast<double *>(win);
-                        const uint32_t idx = l * A.copies + cp;
-                        lds_add_f64(&s[idx], w);
-                        lds_add_f64(&s[wlen * A.copies + idx], w * w);
-                    } else {
-                        float *s = reinterpret_cast<float *>(win);
-                        const uint32_t n1 = wlen * A.copies;
-                        const uint32_t idx = l * A.copies + cp;
-                        const float wf = (float)wv[j];
-                        const float w2 = wf * wf;
-                        const float e2 = __builtin_fmaf(wf, wf, -w2);   // exact: wf*wf = w2 + e2
-                        const float o1 = lds_add_rtn_f32(&s[idx], wf);
-                        const float c1 = two_sum_err(o1, wf);
-                        const float o2 = lds_add_rtn_f32(&s[2 * n1 + idx], w2);
-                        const float c2 = two_sum_err(o2, w2) + e2;
-                        lds_add_f32(&s[n1 + idx], c1);
-                        lds_add_f32(&s[3 * n1 + idx], c2);
-                    }
-                } else if (W) {
-                    gl_add_f64(&A.sumw[g], w);
-                    gl_add_f64(&A.sumw2[g], w * w);
-                } else {
-                    gl_add_u64(&A.cnt[g], 1ull);
-                }
-            }
-        }
+    for (int a = 0; a < D; ++a)
+        xb[a] = static_cast<const T *>(A.coords[a]) + start;
+    const T *wb = W ? static_cast<const T *>(A.w) + start : nullptr;
+    T cx[U][D], cw[U];
+    if (nfull > 0)
+        load_batch<D, T, W, U, false>(xb, wb, 0, len, cx, cw);
+    else
+        load_batch<D, T, W, U, true>(xb, wb, 0, len, cx, cw);
+    for (uint32_t k = 0, base = 0; base < len; ++k, base += step) {
+        T nx[U][D], nw[U];
+        if (k + 1 < nfull)
+            load_batch<D, T, W, U, false>(xb, wb, base + step, len, nx, nw);
+        else
+            load_batch<D, T, W, U, true>(xb, wb, base + step, len, nx, nw);
+        process_batch<D, T, ACC, W, U, KS>(A, smem, win, cx, cw, base, len, cp, st);
         if (ACC == ACC_U16 && ++it == A.epoch_iters) {
             it = 0;
             __syncthreads();
             drain_u16(win, words, A.win_lo, A.cnt);
             __syncthreads();
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+                cx[j][a] = nx[j][a];
+            cw[j] = nw[j];
         }
     }
     __syncthreads();
@@ -562,46 +618,75 @@ static void allow_big_lds(K kernel)
         (void)hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
 }
 
-template <int D, typename T, int ACC, bool W>
+template <int D, typename T, int ACC, bool W, int KS>
 static hipError_t launch_fill_t(int threads, int blocks, size_t lds, const FillArgs &a,
                                 hipStream_t s)
 {
-    auto k = fill_kernel<D, T, ACC, W, fill_unroll(D, sizeof(T) == 4)>;
+    auto k = fill_kernel<D, T, ACC, W, fill_unroll(D, sizeof(T) == 4, W), KS>;
     allow_big_lds(k);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
 }
 
-template <int D, typename T>
-static hipError_t launch_fill_d(int acc, bool weighted, int threads, int blocks, size_t lds,
+template <int D, typename T, int KS>
+static hipError_t launch_fill_k(int acc, bool weighted, int threads, int blocks, size_t lds,
                                 const FillArgs &a, hipStream_t s)
 {
     if (!weighted) {
         if (acc == ACC_U32)
-            return launch_fill_t<D, T, ACC_U32, false>(threads, blocks, lds, a, s);
+            return launch_fill_t<D, T, ACC_U32, false, KS>(threads, blocks, lds, a, s);
         if (acc == ACC_U16)
-            return launch_fill_t<D, T, ACC_U16, false>(threads, blocks, lds, a, s);
+            return launch_fill_t<D, T, ACC_U16, false, KS>(threads, blocks, lds, a, s);
         return hipErrorInvalidValue;
     }
     if (acc == ACC_F64)
-        return launch_fill_t<D, T, ACC_F64, true>(threads, blocks, lds, a, s);
+        return launch_fill_t<D, T, ACC_F64, true, KS>(threads, blocks, lds, a, s);
     if constexpr (sizeof(T) == 4) {
         if (acc == ACC_F32C)
-            return launch_fill_t<D, T, ACC_F32C, true>(threads, blocks, lds, a, s);
+            return launch_fill_t<D, T, ACC_F32C, true, KS>(threads, blocks, lds, a, s);
     }
     return hipErrorInvalidValue;
+}
+
+template <int D, typename T>
+static hipError_t launch_fill_d(int acc, bool weighted, int ks, int threads, int blocks,
+                                size_t lds, const FillArgs &a, hipStream_t s)
+{
+    if (ks == KS_UNIFORM)
+        return launch_fill_k<D, T, KS_UNIFORM>(acc, weighted, threads, blocks, lds, a, s);
+    if constexpr (D == 1) {
+        if (ks == KS_LEARNED1)
+            return launch_fill_k<D, T, KS_LEARNED1>(acc, weighted, threads, blocks, lds, a, s);
+        return launch_fill_k<D, T, KS_BSEARCH1>(acc, weighted, threads, blocks, lds, a, s);
+    } else {
+        return launch_fill_k<D, T, KS_MIXED>(acc, weighted, threads, blocks, lds, a, s);
+    }
+}
+
+// Kernel specialization for the axis kinds of a fill.
+static int kind_set(int dims, const FillArgs &a)
+{
+    bool all_uniform = true;
+    for (int d = 0; d < dims; ++d)
+        all_uniform = all_uniform && a.ax[d].kind == AX_UNIFORM;
+    if (all_uniform)
+        return KS_UNIFORM;
+    if (dims == 1)
+        return a.ax[0].kind == AX_LEARNED ? KS_LEARNED1 : KS_BSEARCH1;
+    return KS_MIXED;
 }
 
 hipError_t launch_fill(int dims, bool f32, int acc, bool weighted, int threads, int blocks,
                        size_t lds, const FillArgs &a, hipStream_t s)
 {
+    const int ks = kind_set(dims, a);
     switch (dims * 2 + (f32 ? 1 : 0)) {
-    case 2: return launch_fill_d<1, double>(acc, weighted, threads, blocks, lds, a, s);
-    case 3: return launch_fill_d<1, float>(acc, weighted, threads, blocks, lds, a, s);
-    case 4: return launch_fill_d<2, double>(acc, weighted, threads, blocks, lds, a, s);
-    case 5: return launch_fill_d<2, float>(acc, weighted, threads, blocks, lds, a, s);
-    case 6: return launch_fill_d<3, double>(acc, weighted, threads, blocks, lds, a, s);
-    case 7: return launch_fill_d<3, float>(acc, weighted, threads, blocks, lds, a, s);
+    case 2: return launch_fill_d<1, double>(acc, weighted, ks, threads, blocks, lds, a, s);
+    case 3: return launch_fill_d<1, float>(acc, weighted, ks, threads, blocks, lds, a, s);
+    case 4: return launch_fill_d<2, double>(acc, weighted, ks, threads, blocks, lds, a, s);
+    case 5: return launch_fill_d<2, float>(acc, weighted, ks, threads, blocks, lds, a, s);
+    case 6: return launch_fill_d<3, double>(acc, weighted, ks, threads, blocks, lds, a, s);
+    case 7: return launch_fill_d<3, float>(acc, weighted, ks, threads, blocks, lds, a, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -215,6 +215,7 @@ extern "C" hist_status hist_create(int dims, const hist_axis *axes, uint32_t fla
             d.xmax = ax.xmax;
             d.width = ax.xmax - ax.xmin;
             d.inv_width = 1.0 / d.width;
+            d.margin = 1e-15 * ((double)ax.nbins + 1.0);
         }
     }
     hipError_t e = dalloc(&h->d_cnt, (size_t)T);
@@ -608,22 +609,31 @@ static int default_segments(int32_t nbins)
     return s;
 }
 
-// Key feature: segments of 2^(52-q) key units, i.e. 2^q segments per binade
-// (power of two) of |x|, aligned so that every binade boundary -- where the
-// key is not linear in x -- is a segment boundary.  The scale 2^(q-41) is a
-// power of two, so t = ((key - key0) >> 11) * fscale is exact.  Picks the
-// largest q whose segment count fits kMaxSegments.
-static void key_segments(double e0, double en, uint64_t &key0, double &fscale, int &nseg)
+// Key feature: the top 32 bits of the order key, cut into segments of
+// 2^(20-q) units, i.e. 2^q segments per binade (power of two) of |x|, aligned
+// so that every binade boundary -- where the key is not linear in x -- is a
+// segment boundary.  The scale 2^(q-20) is a power of two, so t is exact.
+// Picks the largest q whose segment count fits kMaxSegments.
+static uint32_t host_order_key32(double x)
 {
-    const uint64_t k0 = host_order_key(e0), k1 = host_order_key(en);
+    return (uint32_t)(host_order_key(x) >> 32);
+}
+
+static void key_segments(double e0, double en, AxisDev &ax)
+{
+    const uint32_t k0 = host_order_key32(e0), k1 = host_order_key32(en);
     for (int q = 20; q >= -11; --q) {
-        const int sh = 52 - q;   // log2 of the segment width in key units
-        const uint64_t k0a = sh >= 64 ? 0 : (k0 & ~((((uint64_t)1) << sh) - 1));
-        const uint64_t count = (sh >= 64 ? 0 : ((k1 - k0a) >> sh)) + 1;
+        const int sh = 20 - q;   // log2 of the segment width in key units, <= 31
+        const uint32_t mask = sh >= 32 ? 0xFFFFFFFFu : ((1u << sh) - 1u);
+        const uint32_t k0a = k0 & ~mask;
+        const uint64_t count = (uint64_t)((k1 - k0a) >> sh) + 1;
         if (count <= (uint64_t)kMaxSegments || q == -11) {
-            key0 = k0a;
-            fscale = std::ldexp(1.0, q - 41);
-            nseg = (int)std::min<uint64_t>(count, (uint64_t)kMaxSegments);
+            ax.key0 = k0a;
+            ax.kshift = sh;
+            ax.kmask = mask;
+            ax.zscale = std::ldexp(1.0f, -sh);
+            ax.nseg = (int)std::min<uint64_t>(count, (uint64_t)kMaxSegments);
+            ax.keypos = e0 > 0.0 ? 1 : 0;
             return;
         }
     }
@@ -641,11 +651,9 @@ extern "C" hist_status hist_train_index(hist_t *h, int axis, void *stream)
     const int32_t n = h->ax[axis].nbins;
     const double e0 = h->edges_host[axis][0];
     const double en = h->edges_host[axis][(size_t)n];
-    int nseg_f[2];
-    uint64_t key0 = 0;
-    double key_scale = 0.0;
-    key_segments(e0, en, key0, key_scale, nseg_f[0]);
-    nseg_f[1] = default_segments(n);
+    AxisDev keyax = h->ax[axis];
+    key_segments(e0, en, keyax);
+    int nseg_f[2] = {keyax.nseg, default_segments(n)};
     const int nseg = std::max(nseg_f[0], nseg_f[1]);
 
     int32_t *d_seg = nullptr;
@@ -662,18 +670,14 @@ extern "C" hist_status hist_train_index(hist_t *h, int axis, void *stream)
     double score[2] = {INFINITY, INFINITY}, maxw[2] = {0, 0}, meanw[2] = {0, 0};
     std::vector<double> diag((size_t)nseg * 2);
     for (int f = 0; f < 2 && e == hipSuccess; ++f) {
-        AxisDev ax = h->ax[axis];
+        AxisDev ax = f == 0 ? keyax : h->ax[axis];
         ax.kind = AX_LEARNED;
         ax.nseg = nseg_f[f];
         ax.feature = f == 0 ? FEAT_KEY : FEAT_LINEAR;
         ax.lds_model = -1;
         ax.x0 = e0;
-        if (f == 0) {
-            ax.key0 = key0;
-            ax.fscale = key_scale;
-        } else {
+        if (f == 1) {
             const double fmax = en - e0;
-            ax.key0 = 0;
             ax.fscale = (std::isfinite(fmax) && fmax > 0) ? (double)ax.nseg / fmax : 0.0;
         }
         ax.model = d_model[f];

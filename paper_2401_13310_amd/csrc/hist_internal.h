@@ -20,13 +20,16 @@ constexpr int kWave = 64;
 enum AxisKind : int32_t { AX_UNIFORM = 0, AX_BSEARCH = 1, AX_LEARNED = 2 };
 enum Feature : int32_t { FEAT_KEY = 0, FEAT_LINEAR = 1 };
 
-// One segment of the learned index: bin position p = a + z (b + c z) over the
-// segment-local feature z, and the offsets that turn p into the candidate
-// interval [ceil(p + clo), floor(p + chi)] that provably holds the bin.
+// One segment of the learned index, 16 bytes (one LDS read): over the
+// segment-local feature z, y = af + z (b + c z) is evaluated in FP32 and the
+// bin provably lies in [ai + ceil(y), ai + floor(y + w)].  c and w are stored
+// as IEEE half in cw (c low, w high); the lower-bound offset is folded into af.
 struct ModelSeg {
-    double a, b, c, clo, chi;
+    float af, b;
+    int32_t ai;
+    uint32_t cw;
 };
-static_assert(sizeof(ModelSeg) == 40, "ModelSeg layout");
+static_assert(sizeof(ModelSeg) == 16, "ModelSeg layout");
 
 struct AxisDev {
     int32_t nbins;
@@ -39,11 +42,17 @@ struct AxisDev {
     const ModelSeg *model;  // device, nseg segments (learned)
     int32_t nseg;
     int32_t feature;        // Feature
-    double fscale;          // segment coordinate t = feature(x) * fscale
-    uint64_t key0;          // feature origin for FEAT_KEY
-    double x0;              // feature origin for FEAT_LINEAR
+    double fscale;          // FEAT_LINEAR: segment coordinate t = (x - x0) * fscale
+    double x0;              // FEAT_LINEAR: feature origin
+    double margin;          // fixed-width axes: fast-path margin, > 4 ulp of nbins
+    uint32_t key0;          // FEAT_KEY: feature origin (a segment boundary)
+    uint32_t kmask;         // FEAT_KEY: 2^kshift - 1
+    int32_t kshift;         // FEAT_KEY: log2 of the segment width in key units
+    float zscale;           // FEAT_KEY: 2^-kshift
+    int32_t keypos;         // FEAT_KEY: e[0] > 0, so every in-range x is positive
     int32_t lds_model;      // byte offset of the model staged in LDS, -1 if none
     int32_t stride;         // product of (nbins+2) of the lower axes
+    int32_t pad;
 };
 
 // --------------------------------------------------------------------------
@@ -51,9 +60,10 @@ struct AxisDev {
 // t = x - xmin, u = nbins * t, v = u / width (each rounded to nearest, no
 // fused multiply-add), bin = 1 + trunc(v) clamped to nbins.  The kernel first
 // guesses v with a multiply by the rounded reciprocal; that guess differs from
-// the correctly rounded quotient by under 3 ulp, so when it lies more than
-// 1e-15 * v (about 9 ulp) away from every integer its floor equals floor(v)
-// and the division is skipped.  Otherwise the exact division decides.
+// the correctly rounded quotient by under 3 ulp of v <= nbins, so when its
+// fractional part is farther than `margin` (1e-15 * (nbins + 1), about 9 ulp
+// of nbins) from 0 and from 1, its floor equals floor(v) and the division is
+// skipped.  Otherwise the exact division decides.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int32_t bin_uniform(double x, const AxisDev &ax)
 {
@@ -62,13 +72,12 @@ __device__ __forceinline__ int32_t bin_uniform(double x, const AxisDev &ax)
         return 0;
     if (!(x < ax.xmax))
         return ax.nbins + 1;
-    double t = x - ax.xmin;
-    double u = ax.nbins_d * t;
-    double q = u * ax.inv_width;
-    double k = __builtin_floor(q);
-    double m = q * 1e-15 + 1e-300;
+    const double t = x - ax.xmin;
+    const double u = ax.nbins_d * t;
+    const double q = u * ax.inv_width;
+    const double k = __builtin_floor(q);
     int32_t b;
-    if ((q - k) > m && ((k + 1.0) - q) > m)
+    if (__builtin_fabs((q - k) - 0.5) < 0.5 - ax.margin)
         b = (int32_t)k + 1;
     else
         b = (int32_t)(u / ax.width) + 1;
@@ -76,108 +85,216 @@ __device__ __forceinline__ int32_t bin_uniform(double x, const AxisDev &ax)
 }
 
 // --------------------------------------------------------------------------
-// Variable axis, binary search.  For e[0] <= x < e[nbins], the bin is one
-// more than the largest index i with e[i] <= x.  The loop runs
-// ceil(log2 nbins) steps for every lane, so a wave never diverges.
+// Variable axis, binary search (search_lockstep below with the interval
+// [1, nbins]): for e[0] <= x < e[nbins] the bin is one more than the largest
+// index i with e[i] <= x, found in ceil(log2 nbins) halving steps.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ int32_t search_edges(double x, const double *__restrict__ e,
-                                                int32_t base, int32_t len)
-{
-    // largest i in [base, base+len) with e[i] <= x, given e[base] <= x
-    while (len > 1) {
-        int32_t half = len >> 1;
-        if (!(x < e[base + half]))
-            base += half;
-        len -= half;
-    }
-    return base;
-}
-
-__device__ __forceinline__ int32_t bin_bsearch(double x, const AxisDev &ax)
-{
-    if (x < ax.xmin)
-        return 0;
-    if (!(x < ax.xmax))
-        return ax.nbins + 1;
-    return search_edges(x, ax.edges, 0, ax.nbins) + 1;
-}
 
 // --------------------------------------------------------------------------
-// Learned index.  Order-preserving feature of x, monotone non-decreasing in x:
-//   FEAT_KEY:    (orderkey(x + 0.0) - key0) >> 11, exact as a double (< 2^53)
-//   FEAT_LINEAR: x - x0, rounded
-// t = feature * fscale (monotone), segment s = min(trunc(t), nseg - 1),
-// z = t - s (monotone within a segment).  The same functions run in the
-// training kernels, so training sees exactly the values inference computes.
+// Learned index.  Segment s and segment-local coordinate z of x, both
+// monotone non-decreasing in x (z within a segment):
+//   FEAT_KEY:    f = top 32 bits of the order-preserving integer key of x
+//                (sign, exponent, 20 mantissa bits -- close to log2|x|) minus
+//                key0; s = f >> kshift, z = (f & kmask) * 2^-kshift.  Segment
+//                boundaries are binade boundaries or finer, where the key is
+//                linear in x.
+//   FEAT_LINEAR: t = (x - x0) * fscale, s = min(trunc(t), nseg - 1),
+//                z = t - s.
+// The training kernels use the same functions, so they see exactly the
+// values inference computes.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t order_key(double x)
+__device__ __forceinline__ uint32_t order_key32(double x)
 {
-    uint64_t k = (uint64_t)__double_as_longlong(x + 0.0);   // -0.0 -> +0.0
-    return (k >> 63) ? ~k : (k | 0x8000000000000000ull);
+    const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(x + 0.0) >> 32);   // -0 -> +0
+    return (hi >> 31) ? ~hi : (hi | 0x80000000u);
 }
 
-__device__ __forceinline__ double feature_t(double x, const AxisDev &ax)
+// f of the key feature; x must be in [e[0], e[nbins]).
+__device__ __forceinline__ uint32_t key_feature(double x, const AxisDev &ax)
 {
-    double f;
-    if (ax.feature == FEAT_KEY)
-        f = (double)(int64_t)((order_key(x) - ax.key0) >> 11);
+    uint32_t k;
+    if (ax.keypos)
+        k = (uint32_t)((uint64_t)__double_as_longlong(x) >> 32) | 0x80000000u;
     else
-        f = x - ax.x0;
-    return f * ax.fscale;
+        k = order_key32(x);
+    return k - ax.key0;
 }
 
-__device__ __forceinline__ int32_t seg_of(double t, int32_t nseg)
+__device__ __forceinline__ void seg_and_z(double x, const AxisDev &ax, int32_t &s, float &z)
 {
-    int32_t s = (int32_t)t;   // t >= 0 for x >= e[0]
-    return s < nseg - 1 ? s : nseg - 1;
+    if (ax.feature == FEAT_KEY) {
+        const uint32_t f = key_feature(x, ax);
+        const uint32_t sf = f >> ax.kshift;
+        s = (int32_t)(sf < (uint32_t)(ax.nseg - 1) ? sf : (uint32_t)(ax.nseg - 1));
+        z = (float)(f - ((uint32_t)s << ax.kshift)) * ax.zscale;
+    } else {
+        const double t = (x - ax.x0) * ax.fscale;
+        const int32_t si = (int32_t)t;
+        s = si < ax.nseg - 1 ? si : ax.nseg - 1;
+        z = (float)(t - (double)s);
+    }
 }
 
-__device__ __forceinline__ double model_eval(const ModelSeg &m, double z)
+__device__ __forceinline__ float half_lo(uint32_t v)
 {
-    return __builtin_fma(__builtin_fma(m.c, z, m.b), z, m.a);
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(v & 0xFFFFu));
 }
-
-// Bin on a variable axis from the learned model `m` (already loaded, from LDS
-// or global memory).  The candidate interval from the segment's bounds always
-// holds the bin; when it has one element no edge is read, otherwise a binary
-// search over that interval reads the edges.  An empty interval cannot occur
-// for a correctly trained model; binary search over all edges answers then.
-__device__ __forceinline__ int32_t bin_learned_with(double x, const AxisDev &ax,
-                                                    const ModelSeg *__restrict__ model)
+__device__ __forceinline__ float half_hi(uint32_t v)
 {
-    if (x < ax.xmin)
-        return 0;
-    if (!(x < ax.xmax))
-        return ax.nbins + 1;
-    double t = feature_t(x, ax);
-    int32_t s = seg_of(t, ax.nseg);
-    double z = t - (double)s;
-    ModelSeg m = model[s];
-    double p = model_eval(m, z);
-    double flo = __builtin_ceil(p + m.clo);
-    double fhi = __builtin_floor(p + m.chi);
-    int32_t lo = flo < 1.0 ? 1 : (flo > ax.nbins_d ? ax.nbins : (int32_t)flo);
-    int32_t hi = fhi > ax.nbins_d ? ax.nbins : (fhi < 1.0 ? 1 : (int32_t)fhi);
-    if (lo == hi)
-        return lo;
-    if (lo > hi)
-        return search_edges(x, ax.edges, 0, ax.nbins) + 1;
-    // bin in [lo, hi]: e[lo-1] <= x < e[hi]; count edges e[lo..hi-1] <= x
-    return search_edges(x, ax.edges, lo - 1, hi - lo + 1) + 1;
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(v >> 16));
 }
 
-// Dispatch on the axis kind (uniform across a wave: no divergence).
+// y = af + z (b + c z), two FP32 fused multiply-adds (the same code in
+// training and inference).
+__device__ __forceinline__ float model_eval(const ModelSeg &m, float z)
+{
+    return __builtin_fmaf(__builtin_fmaf(half_lo(m.cw), z, m.b), z, m.af);
+}
+
+// Candidate interval [lo, hi] of the bin of x on a variable axis from the
+// learned model (from LDS or global memory).  Underflow and overflow give
+// lo = hi = 0 or nbins+1.  The interval always holds the bin (see learned.hip);
+// an empty interval cannot occur for a correctly trained model, and the full
+// range [1, nbins] is searched then.
+__device__ __forceinline__ void learned_interval(double x, const AxisDev &ax,
+                                                 const ModelSeg *__restrict__ model,
+                                                 int32_t &lo, int32_t &hi)
+{
+    if (x < ax.xmin) {
+        lo = hi = 0;
+        return;
+    }
+    if (!(x < ax.xmax)) {
+        lo = hi = ax.nbins + 1;
+        return;
+    }
+    int32_t s;
+    float z;
+    seg_and_z(x, ax, s, z);
+    const ModelSeg m = model[s];
+    const float y = model_eval(m, z);
+    // clamp before converting so ai + offset stays in int32 (an infinite width
+    // becomes the whole axis)
+    const float ylo = __builtin_fminf(__builtin_fmaxf(__builtin_ceilf(y), -0x1p30f), 0x1p30f);
+    const float yhi = __builtin_fminf(__builtin_fmaxf(__builtin_floorf(y + half_hi(m.cw)), -0x1p30f), 0x1p30f);
+    const int32_t l = m.ai + (int32_t)ylo;
+    const int32_t h = m.ai + (int32_t)yhi;
+    lo = l < 1 ? 1 : (l > ax.nbins ? ax.nbins : l);
+    hi = h < 1 ? 1 : (h > ax.nbins ? ax.nbins : h);
+    if (lo > hi) {
+        lo = 1;
+        hi = ax.nbins;
+    }
+}
+
+// Resolves U searches at once: each bin is known to lie in [lo, hi] with
+// e[lo-1] <= x < e[hi].  Intervals of two candidates (the common case after
+// the learned index) take one compare with e[lo]; wider ones halve per step.
+// The edge loads of all U events of a step are issued together so their
+// latencies overlap.  Reads only e[1 .. nbins-1].
+template <int U>
+__device__ __forceinline__ void search_lockstep(const double (&x)[U], const double *__restrict__ e,
+                                                int32_t (&lo)[U], int32_t (&hi)[U])
+{
+    bool wide = false;
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        wide = wide || hi[j] - lo[j] > 1;
+    if (!wide) {
+        double ev[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (hi[j] > lo[j])
+                ev[j] = e[lo[j]];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (hi[j] > lo[j])
+                lo[j] += (x[j] < ev[j]) ? 0 : 1;
+        return;
+    }
+    bool open = false;
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        open = open || lo[j] < hi[j];
+    while (open) {
+        double ev[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (lo[j] < hi[j])
+                ev[j] = e[((lo[j] + hi[j] + 1) >> 1) - 1];
+        open = false;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (lo[j] < hi[j]) {
+                const int32_t m = (lo[j] + hi[j] + 1) >> 1;
+                if (!(x[j] < ev[j]))
+                    lo[j] = m;
+                else
+                    hi[j] = m - 1;
+                open = open || lo[j] < hi[j];
+            }
+        }
+    }
+}
+
+// Bins of U coordinates on one axis.  KIND is the axis kind when known at
+// compile time, or -1 to dispatch on ax.kind (uniform across a wave).
+// `smem` is the kernel's dynamic LDS array, holding the staged learned models.
+template <int U, int KIND = -1>
+__device__ __forceinline__ void axis_bins(const double (&x)[U], const AxisDev &ax,
+                                          const char *smem, int32_t (&b)[U])
+{
+    const int kind = KIND >= 0 ? KIND : ax.kind;
+    if (kind == AX_UNIFORM) {
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            b[j] = bin_uniform(x[j], ax);
+        return;
+    }
+    int32_t lo[U], hi[U];
+    if (kind == AX_LEARNED) {
+        // kernels always stage the model in LDS; deriving the pointer from the
+        // LDS array keeps these reads ds_read instructions (not flat loads)
+        const ModelSeg *m = reinterpret_cast<const ModelSeg *>(smem + ax.lds_model);
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            learned_interval(x[j], ax, m, lo[j], hi[j]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (x[j] < ax.xmin) {
+                lo[j] = hi[j] = 0;
+            } else if (!(x[j] < ax.xmax)) {
+                lo[j] = hi[j] = ax.nbins + 1;
+            } else {
+                lo[j] = 1;
+                hi[j] = ax.nbins;
+            }
+        }
+    }
+    search_lockstep<U>(x, ax.edges, lo, hi);
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        b[j] = lo[j];
+}
+
+// Kernel specializations by the kinds of the axes.
+enum KindSet : int32_t { KS_UNIFORM = 0, KS_LEARNED1 = 1, KS_BSEARCH1 = 2, KS_MIXED = 3 };
+
+template <int KS>
+__host__ __device__ constexpr int kind_of_set()
+{
+    return KS == KS_UNIFORM ? AX_UNIFORM
+                            : (KS == KS_LEARNED1 ? AX_LEARNED : (KS == KS_BSEARCH1 ? AX_BSEARCH : -1));
+}
+
+// Single coordinate.
 __device__ __forceinline__ int32_t axis_bin(double x, const AxisDev &ax, const char *smem)
 {
-    if (ax.kind == AX_UNIFORM)
-        return bin_uniform(x, ax);
-    if (ax.kind == AX_LEARNED) {
-        const ModelSeg *m = ax.lds_model >= 0
-                                ? reinterpret_cast<const ModelSeg *>(smem + ax.lds_model)
-                                : ax.model;
-        return bin_learned_with(x, ax, m);
-    }
-    return bin_bsearch(x, ax);
+    double xs[1] = {x};
+    int32_t b[1];
+    axis_bins<1>(xs, ax, smem, b);
+    return b[0];
 }
 
 }  // namespace hg

@@ -32,7 +32,12 @@ constexpr int kMaxThreads = 1024;
 constexpr int kTileUnroll = 4;
 
 // Events each thread loads per loop iteration of the fill kernel.
-__host__ __device__ constexpr int fill_unroll(int D, bool f32) { return (D == 1 || f32) ? 8 : 4; }
+// Sized so the double-buffered batch fits the 128 VGPRs a 1024-thread
+// workgroup allows without spilling.
+__host__ __device__ constexpr int fill_unroll(int D, bool f32, bool weighted)
+{
+    return D == 1 ? ((weighted && !f32) ? 4 : 8) : (D == 2 ? 4 : 2);
+}
 
 struct FillArgs {
     AxisDev ax[kMaxDims];

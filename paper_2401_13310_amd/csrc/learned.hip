@@ -7,12 +7,14 @@
 // segment-local feature z on training pairs made from the edge array by the
 // find-bin rule (edge e_i lies at the start of bin i+1; the midpoint of bin
 // i+1 lies half a bin further), and stores error bounds measured at every
-// edge the segment can see.  Because the feature, the segment map and the
-// model are all monotone non-decreasing and the Horner rounding error is
-// bounded, the bin of any x in the segment lies in
-//   [ceil(p(z) + clo), floor(p(z) + chi)]
-// so the search that follows is exact; when that interval has one element no
-// edge is read at all.
+// edge the segment can see.  The segment map and z are monotone in x, the
+// stored quadratic is checked to be monotone over the z range of those edges,
+// and the FP32 Horner rounding is bounded by gamma = 4u (1 + |b||z| + |c|z^2),
+// so for any x in the segment the bin lies in
+//   [ai + ceil(y(z)), ai + floor(y(z) + w)]
+// with the lower-bound offset folded into the intercept and w rounded up.  The
+// search that follows is exact; when that interval has one element no edge is
+// read at all.
 #include "kernels.h"
 
 namespace hg {
@@ -21,7 +23,12 @@ __global__ void seg_of_edges_kernel(const AxisDev ax, int32_t *seg)
 {
     const int32_t ne = ax.nbins + 1;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += blockDim.x * gridDim.x)
-        seg[i] = seg_of(feature_t(ax.edges[i], ax), ax.nseg);
+    {
+        int32_t sg;
+        float z;
+        seg_and_z(ax.edges[i], ax, sg, z);
+        seg[i] = sg;
+    }
 }
 
 // first index i in [0, n) with seg[i] >= s (seg is non-decreasing)
@@ -88,10 +95,16 @@ __device__ void block_minmax(double &mn, double &mx, double &gm, double *red)
     __syncthreads();
 }
 
-// z of x relative to segment s, exactly as inference computes it.
-__device__ __forceinline__ double z_in_seg(double x, const AxisDev &ax, int32_t s)
+// z of x relative to segment s: for x in segment s exactly the value inference
+// computes, and a monotone extension of it for the neighbouring edges.
+__device__ __forceinline__ float z_in_seg(double x, const AxisDev &ax, int32_t s)
 {
-    return feature_t(x, ax) - (double)s;
+    if (ax.feature == FEAT_KEY) {
+        const int64_t d = (int64_t)key_feature(x, ax) - ((int64_t)s << ax.kshift);
+        return (float)d * ax.zscale;
+    }
+    const double t = (x - ax.x0) * ax.fscale;
+    return (float)(t - (double)s);
 }
 
 // One workgroup per segment.  diag[2*s] = candidate-interval width, diag[2*s+1]
@@ -117,7 +130,7 @@ __global__ void __launch_bounds__(256) fit_segments_kernel(const AxisDev ax, con
                 break;
             const double x = h == 0 ? e[i] : 0.5 * e[i] + 0.5 * e[i + 1];
             const double y = (double)i + (h == 0 ? 1.0 : 1.5) - ymid;
-            const double z = z_in_seg(x, ax, s);
+            const double z = (double)z_in_seg(x, ax, s);
             const double z2 = z * z;
             v[0] += 1.0;
             v[1] += z;
@@ -177,12 +190,17 @@ __global__ void __launch_bounds__(256) fit_segments_kernel(const AxisDev ax, con
             }
         }
     }
-    // z range of the evaluated edges: monotone model there, else linear
-    double zmin = z_in_seg(e[j0], ax, s);
-    double zmax = z_in_seg(e[j1], ax, s);
-    if (!(b + 2.0 * c * zmin >= 0.0) || !(b + 2.0 * c * zmax >= 0.0) || !isfinite(a)) {
+    // Stored coefficients: b in FP32, c in half.  The exact polynomial must be
+    // monotone over the z range of the evaluated edges, else fall back to a
+    // linear (then constant) model.
+    const double zmin = (double)z_in_seg(e[j0], ax, s);
+    const double zmax = (double)z_in_seg(e[j1], ax, s);
+    float bq = (float)b;
+    float cq = (float)(_Float16)c;
+    if (!((double)bq + 2.0 * (double)cq * zmin >= 0.0) || !((double)bq + 2.0 * (double)cq * zmax >= 0.0) ||
+        !isfinite(a) || !isfinite(bq) || !isfinite(cq)) {
         const double den = v[0] * v[2] - v[1] * v[1];
-        c = 0.0;
+        cq = 0.0f;
         if (den > 1e-300 && v[0] >= 2.0) {
             b = (v[0] * v[6] - v[1] * v[5]) / den;
             a = (v[5] - b * v[1]) / v[0];
@@ -190,37 +208,57 @@ __global__ void __launch_bounds__(256) fit_segments_kernel(const AxisDev ax, con
             b = 0.0;
             a = v[0] > 0 ? v[5] / v[0] : 0.0;
         }
-        if (!(b >= 0.0) || !isfinite(b)) {
-            b = 0.0;
+        bq = (float)b;
+        if (!(bq >= 0.0f) || !isfinite(bq)) {
+            bq = 0.0f;
             a = v[0] > 0 ? v[5] / v[0] : 0.0;
         }
     }
     a += ymid;
+    const double ai0 = floor(a);
     ModelSeg m;
-    m.a = a;
-    m.b = b;
-    m.c = c;
-    m.clo = 0.0;
-    m.chi = 0.0;
+    m.af = (float)(a - ai0);
+    m.b = bq;
+    m.ai = 0;
+    m.cw = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)cq);
 
-    // residuals at every evaluated edge, and the Horner error bound
+    // residuals of ai0 + y(z) at every evaluated edge (the FP32 evaluation
+    // inference performs), and the FP32 Horner error bound gamma
     double dlo = 1e300, dhi = -1e300, gmax = 0.0;
     for (int32_t i = j0 + (int32_t)threadIdx.x; i <= j1; i += blockDim.x) {
-        const double z = z_in_seg(e[i], ax, s);
-        const double p = model_eval(m, z);
+        const float z = z_in_seg(e[i], ax, s);
+        const double p = ai0 + (double)model_eval(m, z);
         const double r = p - (double)(i + 1);
         dlo = fmin(dlo, r);
         dhi = fmax(dhi, r);
-        gmax = fmax(gmax, fabs(a) + fabs(b) * fabs(z) + fabs(c) * z * z);
+        // |af| <= 1 both before and after the lower bound is folded into it
+        gmax = fmax(gmax, 1.0 + fabs((double)bq) * fabs((double)z) +
+                              fabs((double)cq) * (double)z * (double)z);
     }
     block_minmax(dlo, dhi, gmax, red);
     if (threadIdx.x == 0) {
-        const double gamma = 4.0 * 0x1p-53 * gmax;   // |fl(p) - p| <= gamma on the segment
-        const double eta = 4e-6;                     // rounding of p + clo, p + chi, residuals
-        m.clo = -1.0 - dhi - 2.0 * gamma - eta;
-        m.chi = -dlo + 2.0 * gamma + eta;
+        const double u = 0x1p-24;
+        const double gamma = 4.0 * u * gmax;               // |fl(y) - y| on the segment
+        const double eta = 8.0 * u * (gmax + 2.0) + 1e-9;  // roundings of y+w, residuals
+        // lower bound: bin >= ai0 + y - 1 - dhi - 2 gamma; fold it into af with
+        // room for the rounding of the folded evaluation
+        const double clo = -1.0 - dhi - 4.0 * gamma - eta;
+        const double tot = (double)m.af + clo;
+        const double fl = floor(tot);
+        m.ai = (int32_t)fmax(-2147483647.0, fmin(2147483647.0, ai0 + fl));
+        m.af = __double2float_rd(tot - fl);
+        // width: bin <= ai0 + y - dlo + 2 gamma
+        const double wdt = (-dlo + 2.0 * gamma) - clo + 4.0 * gamma + eta;
+        _Float16 wh = (_Float16)wdt;
+        if ((double)(float)wh < wdt) {
+            uint16_t bits = __builtin_bit_cast(uint16_t, wh);
+            wh = __builtin_bit_cast(_Float16, (uint16_t)(bits + 1));   // next half up (to +inf past max)
+        }
+        if (!(wdt < 65504.0))
+            wh = __builtin_bit_cast(_Float16, (uint16_t)0x7C00);        // +inf: search the whole axis
+        m.cw = (m.cw & 0xFFFFu) | ((uint32_t)__builtin_bit_cast(uint16_t, wh) << 16);
         model[s] = m;
-        diag[2 * s] = m.chi - m.clo;
+        diag[2 * s] = (double)(float)wh;
         diag[2 * s + 1] = (double)(hi_s - lo_s);
     }
 }

@@ -11,7 +11,7 @@
 
 namespace hg {
 
-constexpr int kMaxSegments = 512;
+constexpr int kMaxSegments = 1024;
 
 // How one fill is launched.
 struct Plan {
@@ -37,6 +37,7 @@ struct PlanChoice {
     int copies = 0;
     int merge = -1;
     int64_t win_lo = -1;
+    int threads = 0;         // threads per workgroup (0: heuristic)
 };
 
 }  // namespace hg
@@ -94,6 +95,6 @@ hist_status run_plan(hist_s *h, const Plan &p, const void *const *coords, const 
 size_t stage_bytes_for(const Plan &p);
 int64_t stage_stride_for(const Plan &p);
 int64_t tiled_chunk(const hist_s *h);
-int unroll_of(int dims, bool f32);
+int unroll_of(int dims, bool f32, bool weighted);
 
 }  // namespace hg

@@ -20,7 +20,7 @@
 
 namespace hg {
 
-int unroll_of(int dims, bool f32) { return fill_unroll(dims, f32); }
+int unroll_of(int dims, bool f32, bool weighted) { return fill_unroll(dims, f32, weighted); }
 
 int apply_model_offsets(const hist_s *h, FillArgs &a)
 {
@@ -75,7 +75,7 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
     const int base = apply_model_offsets(h, probe);
     const int avail = h->lds_max - base;
     p.lds_base = base;
-    p.threads = 1024;
+    p.threads = c.threads > 0 ? c.threads : 1024;
 
     int acc;
     if (weighted)
@@ -143,7 +143,7 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
         p.lds = base + window_bytes(acc, len, copies);
     }
 
-    const int U = fill_unroll(h->dims, f32);
+    const int U = fill_unroll(h->dims, f32, weighted);
     const int64_t step = (int64_t)p.threads * U;
     int bpc = c.blocks_per_cu > 0 ? c.blocks_per_cu : (p.lds > h->lds_max / 2 ? 1 : 2);
     if (p.lds * bpc > h->lds_max)
@@ -234,7 +234,18 @@ extern "C" hist_status hist_set_strategy(hist_t *h, int strategy, int blocks, in
     c.copies = subhists;
     c.merge = h->forced.merge;
     c.win_lo = h->forced.win_lo;
+    c.threads = h->forced.threads;
     h->forced = c;
+    return HIST_OK;
+}
+
+extern "C" hist_status hist_set_threads(hist_t *h, int threads)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_set_threads: NULL handle");
+    if (threads != 0 && threads != 256 && threads != 512 && threads != 1024)
+        return set_error(HIST_EINVAL, "hist_set_threads: 0, 256, 512 or 1024");
+    h->forced.threads = threads;
     return HIST_OK;
 }
 
@@ -385,14 +396,17 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
         if (strat == HIST_STRAT_TILED && p0.acc != ACC_U16 && h->T * 16 <= h->lds_max)
             continue;
         if (strat == HIST_STRAT_LDS) {
-            for (int bpc : {1, 2}) {
-                for (int merge : {MERGE_ATOMIC, MERGE_STAGE}) {
-                    PlanChoice c;
-                    c.strategy = strat;
-                    c.blocks_per_cu = bpc;
-                    c.merge = merge;
-                    c.win_lo = win_lo;
-                    cands.push_back(c);
+            for (int thr : {512, 1024}) {
+                for (int bpc : {1, 2}) {
+                    for (int merge : {MERGE_ATOMIC, MERGE_STAGE}) {
+                        PlanChoice c;
+                        c.strategy = strat;
+                        c.blocks_per_cu = bpc;
+                        c.merge = merge;
+                        c.win_lo = win_lo;
+                        c.threads = thr;
+                        cands.push_back(c);
+                    }
                 }
             }
         } else {
