@@ -1,36 +1,423 @@
-// batch.hip -- batched filling of many histograms (placeholder until the
-// persistent kernel lands).
+// batch.hip -- many histograms filled by one persistent launch, replayed from
+// a HIP graph.
+//
+// The paper leaves several histograms per event loop to future work
+// (arXiv:2401.13310 Sec. 6) and finds that small kernels and launch overhead
+// dominate its single-histogram GPU path (Sec. 6).  Here every member of a
+// batch (its own dims, axes, event count and weights) is cut into tiles of
+// events; one persistent grid takes tiles from an atomic queue in decreasing
+// size order.  For each tile a workgroup privatizes the member's bins in LDS
+// when they fit (else it uses global atomics), finds bins and accumulates as
+// the single-histogram kernel does (Sec. 3.1 steps 1-3), and merges its LDS
+// copy and statistics with atomics -- tiles of one member run concurrently on
+// several CUs.  The last workgroup to finish resets the queue, so the graph
+// holds a single kernel node and replays need no memset.
+#include "device_common.h"
 #include "plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+namespace hg {
+
+struct MemberDev {
+    AxisDev ax[kMaxDims];
+    const void *coords[kMaxDims];
+    const void *w;
+    int64_t n;
+    uint64_t *cnt;
+    double *sumw, *sumw2, *stats;
+    int32_t dims, f32, acc;       // acc: ACC_U32 / ACC_F64, or -1 for global atomics only
+    int32_t win_len, copies, pad;
+};
+
+struct TileDev {
+    int64_t start;
+    int32_t len;
+    int32_t member;
+};
+
+// Events [start, start+len) of member M: find bin, statistics, accumulation.
+template <bool F32, bool W>
+__device__ void batch_events(const MemberDev &M, int64_t start, int32_t len, const char *smem,
+                             uint32_t *win, double (&st)[kMaxStats])
+{
+    using T = typename std::conditional<F32, float, double>::type;
+    const int dims = M.dims;
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    const int C = M.copies;
+    const int cp = tid % C;
+    const uint32_t wlen = M.acc >= 0 ? (uint32_t)M.win_len : 0u;
+    constexpr int U = 2;
+    for (int32_t base = 0; base < len; base += nthr * U) {
+        T xv[U][kMaxDims];
+        T wv[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const int32_t i = base + j * nthr + tid;
+            const bool ok = i < len;
+            for (int a = 0; a < kMaxDims; ++a)
+                xv[j][a] = (ok && a < dims)
+                               ? __builtin_nontemporal_load(static_cast<const T *>(M.coords[a]) + start + i)
+                               : T(0);
+            wv[j] = (W && ok) ? __builtin_nontemporal_load(static_cast<const T *>(M.w) + start + i) : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (base + j * nthr + tid >= len)
+                continue;
+            double x[kMaxDims] = {0.0, 0.0, 0.0};
+            int32_t g = 0;
+            bool inside = true;
+            for (int a = 0; a < dims; ++a) {
+                x[a] = (double)xv[j][a];
+                const int32_t b = axis_bin(x[a], M.ax[a], smem);
+                inside = inside && (uint32_t)(b - 1) < (uint32_t)M.ax[a].nbins;
+                g += (a == 0) ? b : b * M.ax[a].stride;
+            }
+            const double w = W ? (double)wv[j] : 1.0;
+            if (inside)
+                stats_add_rt(st, x, w, dims);
+            if ((uint32_t)g < wlen) {
+                if (W) {
+                    double *s = reinterpret_cast<double *>(win);
+                    const uint32_t idx = (uint32_t)g * C + cp;
+                    lds_add_f64(&s[idx], w);
+                    lds_add_f64(&s[wlen * C + idx], w * w);
+                } else {
+                    lds_add_u32(&win[(uint32_t)g * C + cp], 1u);
+                }
+            } else if (W) {
+                gl_add_f64(&M.sumw[g], w);
+                gl_add_f64(&M.sumw2[g], w * w);
+            } else {
+                gl_add_u64(&M.cnt[g], 1ull);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kMaxThreads)
+batch_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ tiles, int ntiles,
+             uint32_t *queue, int lds_win)
+{
+    extern __shared__ __align__(16) char smem[];
+    __shared__ int s_tile;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    uint32_t *win = reinterpret_cast<uint32_t *>(smem + lds_win);
+    for (;;) {
+        if (tid == 0)
+            s_tile = (int)__hip_atomic_fetch_add(&queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
+        __syncthreads();
+        if (t >= ntiles)
+            break;
+        const TileDev tile = tiles[t];
+        const MemberDev &M = members[__builtin_amdgcn_readfirstlane(tile.member)];
+        // stage the member's learned models, zero its LDS copy
+        for (int a = 0; a < M.dims; ++a) {
+            if (M.ax[a].kind == AX_LEARNED) {
+                const uint4 *src = reinterpret_cast<const uint4 *>(M.ax[a].model);
+                uint4 *dst = reinterpret_cast<uint4 *>(smem + M.ax[a].lds_model);
+                for (int i = tid; i < M.ax[a].nseg; i += nthr)
+                    dst[i] = src[i];
+            }
+        }
+        const int words = M.acc < 0 ? 0 : (M.acc == ACC_U32 ? M.win_len * M.copies : M.win_len * M.copies * 4);
+        for (int i = tid; i < words; i += nthr)
+            win[i] = 0u;
+        __syncthreads();
+        double st[kMaxStats];
+        for (int k = 0; k < kMaxStats; ++k)
+            st[k] = 0.0;
+        const bool weighted = M.w != nullptr;
+        if (M.f32) {
+            if (weighted)
+                batch_events<true, true>(M, tile.start, tile.len, smem, win, st);
+            else
+                batch_events<true, false>(M, tile.start, tile.len, smem, win, st);
+        } else {
+            if (weighted)
+                batch_events<false, true>(M, tile.start, tile.len, smem, win, st);
+            else
+                batch_events<false, false>(M, tile.start, tile.len, smem, win, st);
+        }
+        __syncthreads();
+        reduce_stats<kMaxStats>(st, reinterpret_cast<double *>(smem), M.stats);
+        // merge the LDS copy
+        if (M.acc == ACC_U32) {
+            for (int l = tid; l < M.win_len; l += nthr) {
+                uint32_t c = 0;
+                for (int r = 0; r < M.copies; ++r)
+                    c += win[l * M.copies + r];
+                if (c)
+                    gl_add_u64(&M.cnt[l], c);
+            }
+        } else if (M.acc == ACC_F64) {
+            const double *d = reinterpret_cast<const double *>(win);
+            const int n1 = M.win_len * M.copies;
+            for (int l = tid; l < M.win_len; l += nthr) {
+                double s = 0.0, s2 = 0.0;
+                for (int r = 0; r < M.copies; ++r) {
+                    s += d[l * M.copies + r];
+                    s2 += d[n1 + l * M.copies + r];
+                }
+                if (s != 0.0 || s2 != 0.0) {
+                    gl_add_f64(&M.sumw[l], s);
+                    gl_add_f64(&M.sumw2[l], s2);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // Every workgroup has drawn past the last tile before it counts itself
+    // done, so the last one can reset the queue for the next launch.
+    if (tid == 0) {
+        const uint32_t d = __hip_atomic_fetch_add(&queue[1], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (d == gridDim.x - 1) {
+            __hip_atomic_store(&queue[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&queue[1], 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+__global__ void zero_u32_kernel(uint32_t *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        p[i] = 0u;
+}
+
+}  // namespace hg
 
 using namespace hg;
 
 struct hist_batch_s {
     int k = 0;
+    std::vector<hist_t *> hs;
+    std::vector<int64_t> n;
+    MemberDev *d_members = nullptr;
+    TileDev *d_tiles = nullptr;
+    uint32_t *d_queue = nullptr;
+    int ntiles = 0;
+    int blocks = 1, threads = 1024;
+    int lds = 0, lds_win = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
+
+static void batch_free(hist_batch_s *b)
+{
+    if (!b)
+        return;
+    if (b->exec)
+        (void)hipGraphExecDestroy(b->exec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    if (b->cap_stream)
+        (void)hipStreamDestroy(b->cap_stream);
+    if (b->d_members)
+        (void)hipFree(b->d_members);
+    if (b->d_tiles)
+        (void)hipFree(b->d_tiles);
+    if (b->d_queue)
+        (void)hipFree(b->d_queue);
+    delete b;
+}
+
+static hipError_t batch_enqueue(hist_batch_s *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(batch_kernel, dim3(b->blocks), dim3(b->threads), (size_t)b->lds, s,
+                       b->d_members, b->d_tiles, b->ntiles, b->d_queue, b->lds_win);
+    return hipGetLastError();
+}
 
 extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fill_desc *descs,
                                          hist_batch_t **out, void *stream)
 {
-    (void)k; (void)hs; (void)descs; (void)stream;
-    if (out)
-        *out = nullptr;
-    return set_error(HIST_ENOTSUP, "hist_batch_create: not available yet");
+    if (!out)
+        return set_error(HIST_EINVAL, "hist_batch_create: out is NULL");
+    *out = nullptr;
+    if (k < 1 || !hs || !descs)
+        return set_error(HIST_EINVAL, "hist_batch_create: need k >= 1 handles and descriptors");
+    for (int i = 0; i < k; ++i) {
+        if (!hs[i])
+            return set_error(HIST_EINVAL, "hist_batch_create: handle %d is NULL", i);
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i])
+                return set_error(HIST_EINVAL, "hist_batch_create: handle %d repeats %d", i, j);
+        const hist_fill_desc &d = descs[i];
+        if (d.n < 0 || (d.dtype != HIST_F64 && d.dtype != HIST_F32))
+            return set_error(HIST_EINVAL, "hist_batch_create: member %d: bad n or dtype", i);
+        if (d.n > 0x7FFFFFFFll * 64)
+            return set_error(HIST_EINVAL, "hist_batch_create: member %d: too many events", i);
+        for (int a = 0; a < hs[i]->dims && d.n > 0; ++a)
+            if (!d.coords[a])
+                return set_error(HIST_EINVAL, "hist_batch_create: member %d: coordinate %d is NULL", i, a);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return set_error(HIST_ECAPTURE, "hist_batch_create: stream is capturing");
+
+    hist_batch_s *b = new (std::nothrow) hist_batch_s();
+    if (!b)
+        return set_error(HIST_ENOMEM, "hist_batch_create: host allocation");
+    b->k = k;
+    b->hs.assign(hs, hs + k);
+    const hist_s *h0 = hs[0];
+
+    // LDS budget: statistics partials, then the largest set of staged models,
+    // then the window of bins
+    int model_bytes = 0;
+    for (int i = 0; i < k; ++i) {
+        int mb = 0;
+        for (int a = 0; a < hs[i]->dims; ++a)
+            if (hs[i]->ax[a].kind == AX_LEARNED)
+                mb += hs[i]->ax[a].nseg * (int)sizeof(ModelSeg);
+        model_bytes = std::max(model_bytes, mb);
+    }
+    b->lds_win = (kRedBytes + model_bytes + 15) & ~15;
+    const int avail = h0->lds_max - b->lds_win - 64;   // room for the kernel's static LDS
+
+    std::vector<MemberDev> mem((size_t)k);
+    std::vector<TileDev> tiles;
+    int max_window_bytes = 0;
+    for (int i = 0; i < k; ++i) {
+        hist_s *h = hs[i];
+        const hist_fill_desc &d = descs[i];
+        MemberDev &m = mem[(size_t)i];
+        std::memset(&m, 0, sizeof(m));
+        int off = kRedBytes;
+        for (int a = 0; a < kMaxDims; ++a) {
+            m.ax[a] = h->ax[a];
+            if (a < h->dims && m.ax[a].kind == AX_LEARNED) {
+                m.ax[a].lds_model = off;
+                off += m.ax[a].nseg * (int)sizeof(ModelSeg);
+            } else {
+                m.ax[a].lds_model = -1;
+            }
+            m.coords[a] = a < h->dims ? d.coords[a] : nullptr;
+        }
+        m.w = d.weights;
+        m.n = d.n;
+        m.cnt = h->d_cnt;
+        m.sumw = h->d_sumw;
+        m.sumw2 = h->d_sumw2;
+        m.stats = h->d_stats;
+        m.dims = h->dims;
+        m.f32 = d.dtype == HIST_F32 ? 1 : 0;
+        const int bytes = d.weights ? 16 : 4;
+        if (h->T * bytes <= avail) {
+            m.acc = d.weights ? ACC_F64 : ACC_U32;
+            m.win_len = (int32_t)h->T;
+            m.copies = 1;
+            max_window_bytes = std::max(max_window_bytes, (int)(h->T * bytes));
+        } else {
+            m.acc = -1;
+            m.win_len = 0;
+            m.copies = 1;
+        }
+        b->n.push_back(d.n);
+        // tiles: LDS members get enough events per tile to amortize the
+        // zeroing and merging of their window
+        const int64_t tile_len = m.acc >= 0 ? std::max<int64_t>(65536, 32 * (int64_t)m.win_len) : 131072;
+        const int64_t nt = (d.n + tile_len - 1) / tile_len;
+        for (int64_t t = 0; t < nt; ++t) {
+            const int64_t s0 = d.n * t / nt, s1 = d.n * (t + 1) / nt;
+            if (s1 > s0)
+                tiles.push_back(TileDev{s0, (int32_t)(s1 - s0), i});
+        }
+    }
+    std::stable_sort(tiles.begin(), tiles.end(),
+                     [](const TileDev &x, const TileDev &y) { return x.len > y.len; });
+    b->ntiles = (int)tiles.size();
+    b->lds = b->lds_win + max_window_bytes;
+    b->threads = 1024;
+    const int bpc = b->lds * 2 <= h0->lds_max ? 2 : 1;
+    b->blocks = std::max(1, std::min(h0->num_cu * bpc, std::max(1, b->ntiles)));
+
+    hipError_t e = hipMalloc(&b->d_members, sizeof(MemberDev) * (size_t)k);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_tiles, sizeof(TileDev) * std::max<size_t>(1, tiles.size()));
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_queue, 2 * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_members, mem.data(), sizeof(MemberDev) * (size_t)k, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !tiles.empty())
+        e = hipMemcpy(b->d_tiles, tiles.data(), sizeof(TileDev) * tiles.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, b->d_queue, 2);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(batch_kernel),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, h0->lds_max - 64);
+    // capture one launch into a graph on a private stream
+    if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = batch_enqueue(b, b->cap_stream);
+        e = hipStreamEndCapture(b->cap_stream, &b->graph);
+        if (le != hipSuccess)
+            e = le;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return set_error(e == hipErrorOutOfMemory ? HIST_ENOMEM : HIST_EDEVICE,
+                         "hist_batch_create: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return HIST_OK;
 }
 
 extern "C" hist_status hist_batch_launch(hist_batch_t *b, void *stream)
 {
-    (void)b; (void)stream;
-    return set_error(HIST_ENOTSUP, "hist_batch_launch: not available yet");
+    if (!b)
+        return set_error(HIST_EINVAL, "hist_batch_launch: NULL batch");
+    if (b->ntiles > 0) {
+        hipError_t e = hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(HIST_EDEVICE, "hist_batch_launch: %s", hipGetErrorString(e));
+        }
+    }
+    for (int i = 0; i < b->k; ++i)
+        b->hs[(size_t)i]->entries += b->n[(size_t)i];
+    return HIST_OK;
 }
 
 extern "C" hist_status hist_batch_launch_eager(hist_batch_t *b, void *stream)
 {
-    (void)b; (void)stream;
-    return set_error(HIST_ENOTSUP, "hist_batch_launch_eager: not available yet");
+    if (!b)
+        return set_error(HIST_EINVAL, "hist_batch_launch_eager: NULL batch");
+    if (b->ntiles > 0) {
+        hipError_t e = batch_enqueue(b, static_cast<hipStream_t>(stream));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return set_error(HIST_EDEVICE, "hist_batch_launch_eager: %s", hipGetErrorString(e));
+        }
+    }
+    for (int i = 0; i < b->k; ++i)
+        b->hs[(size_t)i]->entries += b->n[(size_t)i];
+    return HIST_OK;
 }
 
 extern "C" hist_status hist_batch_destroy(hist_batch_t *b)
 {
-    delete b;
+    if (!b)
+        return HIST_OK;
+    (void)hipDeviceSynchronize();
+    batch_free(b);
     return HIST_OK;
 }

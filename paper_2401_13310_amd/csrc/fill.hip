@@ -18,106 +18,13 @@
 //   - small histograms keep up to 64 interleaved copies so the 64 lanes of a
 //     wave that hit the same bin update different LDS words (no serialized
 //     same-address atomics).
+#include "device_common.h"
 #include "kernels.h"
 
 #include <mutex>
 #include <unordered_set>
 
 namespace hg {
-
-template <int D>
-struct NStats {
-    static constexpr int v = 2 + 2 * D + D * (D - 1) / 2;
-};
-
-__device__ __forceinline__ void lds_add_u32(uint32_t *p, uint32_t v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_add_f64(double *p, double v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ float lds_add_rtn_f32(float *p, float v)
-{
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_add_f32(float *p, float v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void gl_add_u64(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void gl_add_f64(double *p, double v)
-{
-    unsafeAtomicAdd(p, v);
-}
-
-// Exact rounding error of fl(a + b) (Knuth's TwoSum).  The sum is formed here,
-// with contraction off, so it is the same rounded value the LDS atomic stored
-// (a product feeding b must not be fused into it).
-__device__ __forceinline__ float two_sum_err(float a, float b)
-{
-#pragma clang fp contract(off)
-    float s = a + b;
-    float bp = s - a;
-    float ap = s - bp;
-    return (a - ap) + (b - bp);
-}
-
-// Per-event statistics terms, rounded in the order w, w*w, w*x, (w*x)*x,
-// (w*x_c)*x_a -- the same products the reference definition forms.
-template <int D>
-__device__ __forceinline__ void stats_add(double (&st)[NStats<D>::v], const double (&x)[D],
-                                          double w)
-{
-#pragma clang fp contract(off)
-    st[0] += w;
-    st[1] += w * w;
-    int k = 2;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        const double wx = w * x[a];
-        st[k++] += wx;
-        st[k++] += wx * x[a];
-#pragma unroll
-        for (int c = 0; c < a; ++c)
-            st[k++] += (w * x[c]) * x[a];
-    }
-}
-
-// Block reduction of the statistics partials, then one binary64 atomic per
-// statistic per workgroup (sums accumulate across fills).
-template <int NS>
-__device__ __forceinline__ void reduce_stats(double (&st)[NS], double *red, double *out)
-{
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const int nw = blockDim.x / kWave;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-        double v = st[k];
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1)
-            v += __shfl_xor(v, off, kWave);
-        st[k] = v;
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < NS; ++k)
-            red[wave * NS + k] = st[k];
-    }
-    __syncthreads();
-    if (threadIdx.x < NS) {
-        double s = 0.0;
-        for (int w = 0; w < nw; ++w)
-            s += red[w * NS + threadIdx.x];
-        if (s != 0.0)
-            gl_add_f64(&out[threadIdx.x], s);
-    }
-}
 
 template <int D>
 __device__ __forceinline__ void stage_models(const AxisDev (&ax)[kMaxDims], char *smem)
