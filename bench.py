@@ -35,13 +35,35 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="variable_1d",
-                    choices=["variable_1d", "plain_1d", "corr_3d", "precision", "paper_1d"])
+                    choices=["variable_1d", "plain_1d", "corr_3d", "precision", "paper_1d",
+                             "batched_64"])
     ap.add_argument("--events", type=int, default=0, help="override the event count")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-bsearch", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM traffic per launch measured with rocprofv3 counters")
+    ap.add_argument("--ingest", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="read two rocprofv3 --pmc databases of a --profile run (FETCH_SIZE, "
+                         "then WRITE_SIZE), scale each by the copy kernel of known size, and "
+                         "record the fill kernel's HBM bytes per launch in --traffic")
+    ap.add_argument("--profile", action="store_true",
+                    help="for counter runs: tune, run --steps fills, then 3 device copies of "
+                         "the coordinate column (a copy of known size to scale the counters); "
+                         "prints the plan, no JSON")
     return ap.parse_args()
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources: counter-derived traffic is valid only for the
+    kernels it was measured on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2401_13310_amd", "csrc")
+    hs = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(d, name), "rb") as f:
+                hs.update(name.encode() + b"\0" + f.read())
+    return hs.hexdigest()[:16]
 
 
 def build_workload(name, events):
@@ -121,19 +143,147 @@ def cpu_baseline(wl, n):
 
 
 def load_traffic(path, workload, n):
+    """HBM bytes per fill launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy
+    of known size), if measured on the current kernel sources."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     rec = t.get(workload)
-    if not rec or rec.get("events") != n:
+    if not rec or rec.get("events") != n or rec.get("source_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
 
 
+def _counter_per_dispatch(db_path, counter):
+    """{kernel name: [value per dispatch]} for one counter of a rocpd database."""
+    import sqlite3
+    db = sqlite3.connect(db_path)
+    per = {}
+    for disp, kname, val in db.execute(
+            "select dispatch_id, kernel_name, sum(value) from counters_collection "
+            "where counter_name = ? group by dispatch_id, kernel_name order by dispatch_id",
+            (counter,)):
+        per.setdefault(kname, []).append(val)
+    return per
+
+
+def ingest(args):
+    fetch = _counter_per_dispatch(args.ingest[0], "FETCH_SIZE")
+    write = _counter_per_dispatch(args.ingest[1], "WRITE_SIZE")
+    copy = [k for k in fetch if "copy" in k.lower() and "hg::" not in k]
+    fill = [k for k in fetch if "fill_kernel" in k]
+    if not copy or not fill:
+        raise SystemExit("ingest: need the fill kernel and the calibration copy in both runs")
+    wl = build_workload(args.workload, args.events)
+    n = wl["coords"][0].size
+    known = n * wl["coords"][0].dtype.itemsize            # bytes read and written by each copy
+    ck = copy[0]
+    f_copy = sorted(fetch[ck])[len(fetch[ck]) // 2] * 1024.0
+    w_copy = sorted(write[ck])[len(write[ck]) // 2] * 1024.0
+    fk = max(fill, key=lambda k: len(fetch[k]))
+    last = max(1, args.steps)                 # the fills after tuning are the last ones
+    fv, wv = sorted(fetch[fk][-last:]), sorted(write[fk][-last:])
+    f_fill = fv[len(fv) // 2] * 1024.0
+    w_fill = wv[len(wv) // 2] * 1024.0
+    sf, sw = known / f_copy, known / w_copy
+    rec = {"events": n, "kernel": fk, "source_hash": kernel_source_hash(),
+           "fetch_kib_raw": f_fill / 1024.0, "write_kib_raw": w_fill / 1024.0,
+           "copy_kernel": ck, "copy_bytes": known, "fetch_scale": sf, "write_scale": sw,
+           "bytes_per_launch": f_fill * sf + w_fill * sw}
+    try:
+        with open(args.traffic) as f:
+            allrec = json.load(f)
+    except (OSError, ValueError):
+        allrec = {}
+    allrec[args.workload] = rec
+    with open(args.traffic, "w") as f:
+        json.dump(allrec, f, indent=1)
+        f.write("\n")
+    print(json.dumps(rec))
+
+
+def bench_batched(args):
+    """64 uneven histograms: one graph replay of the persistent batch kernel
+    against 64 separate plain fills (binary search, global atomics) and 64
+    separate default fills."""
+    import numpy as np
+    import torch
+
+    import paper_2401_13310_amd as hg
+    import synth
+
+    members = synth.batched_64(n_scale=1.0 if not args.events else args.events / 9.3e7)
+    cols, ws, nev, B = [], [], 0, 0
+    for m in members:
+        cols.append([torch.from_numpy(c).to("cuda") for c in m["coords"]])
+        ws.append(torch.from_numpy(m["weights"]).to("cuda"))
+        n = m["weights"].size
+        nev += n
+        T = 1
+        for a in m["axes"]:
+            T *= a["nbins"] + 2
+            if a.get("edges") is not None:
+                B += 8 * (a["nbins"] + 1)
+        B += n * 8 * (len(m["axes"]) + 1) + 16 * T
+
+    def make(learned):
+        hs = []
+        for m in members:
+            h = hg.Hist(m["axes"])
+            if learned:
+                for a, ax in enumerate(m["axes"]):
+                    if ax.get("edges") is not None:
+                        h.train_index(a)
+            hs.append(h)
+        return hs
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    hs = make(True)
+    batch = hg.Batch(hs, cols, ws)
+    ms_graph = timed(lambda: batch.launch(graph=True), args.steps, args.warmup)
+    plain = make(False)
+    for h in plain:
+        h.set_strategy(hg.HIST_STRAT_GLOBAL)
+    ms_plain = timed(lambda: [h.fill(c, w) for h, c, w in zip(plain, cols, ws)], max(2, args.steps // 4), 1)
+    deflt = make(True)
+    ms_default = timed(lambda: [h.fill(c, w) for h, c, w in zip(deflt, cols, ws)], max(2, args.steps // 4), 1)
+    value = nev / (ms_graph * 1e-3)
+    out = {
+        "metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded numpy PCG64)",
+        "config": {"workload": "batched_64: 64 histograms, dims 1-3, log-uniform bins and events, "
+                               "%d events, FP64 weights" % nev},
+        "roofline": {"bound": "hbm", "achieved": B / (ms_graph * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": B / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": None, "kernel": "batch_kernel", "alg_bytes_per_launch": B},
+        "plain_fills": {"value": nev / (ms_plain * 1e-3), "ms_per_step": ms_plain,
+                        "what": "64 hist_fill calls, binary search, global atomics"},
+        "default_fills": {"value": nev / (ms_default * 1e-3), "ms_per_step": ms_default,
+                          "what": "64 hist_fill calls, learned index, heuristic plans"},
+        "speedup_vs_plain": ms_plain / ms_graph,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.ingest:
+        ingest(args)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
@@ -144,6 +294,9 @@ def main():
     import paper_2401_13310_amd as hg
 
     torch.cuda.set_device(0)
+    if args.workload == "batched_64":
+        bench_batched(args)
+        return
     wl = build_workload(args.workload, args.events)
     n = wl["coords"][0].size
     cols = [torch.from_numpy(c).to("cuda") for c in wl["coords"]]
@@ -165,11 +318,26 @@ def main():
     h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
     plan = h.plan_info(n, hg.HIST_F32 if wl["coords"][0].dtype == np.float32 else hg.HIST_F64,
                        w is not None)
+    if args.profile:
+        for _ in range(args.steps):
+            h.fill(cols, w)
+        torch.cuda.synchronize()
+        dst = torch.empty_like(cols[0])
+        for _ in range(3):
+            dst.copy_(cols[0])
+        torch.cuda.synchronize()
+        print("profile run: %d fills of %d events, plan %s; copy of %d bytes x3; sources %s"
+              % (args.steps, n, plan, cols[0].numel() * cols[0].element_size(),
+                 kernel_source_hash()), flush=True)
+        h.close()
+        return
 
     wall, kt = time_fills(hg, h, cols, w, args.steps, args.warmup)
     ms_step = wall / args.steps * 1e3
     value = n * args.steps / wall
     fill_ms = kt["fill_ms"] / max(1, kt["launches"])
+    if fill_ms <= 0:
+        fill_ms = ms_step
     merge_ms = kt["merge_ms"] / max(1, kt["launches"])
     B, per_event = alg_bytes(wl, n)
     achieved = B / (fill_ms * 1e-3) / 1e9

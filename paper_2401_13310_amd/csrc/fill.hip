@@ -139,6 +139,76 @@ __device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A)
     }
 }
 
+// Update of a bin outside the LDS window: first a small LDS cache of hot
+// bins (flow bins, spikes), open addressing with one probe, slots claimed
+// with compare-and-swap; otherwise a global atomic.  Many workgroups hitting
+// one global address serialize in L2, so a hot bin outside the window would
+// otherwise cost far more than its share.
+template <bool W>
+__device__ __forceinline__ void spill(const FillArgs &A, char *smem, int32_t g, double w)
+{
+    if (A.lds_cache >= 0) {
+        uint32_t *keys = reinterpret_cast<uint32_t *>(smem + A.lds_cache);
+        const uint32_t h = ((uint32_t)g * 2654435761u) >> 16 & (uint32_t)(A.cache_slots - 1);
+        uint32_t k = keys[h];
+        if (k == kCacheEmpty) {
+            uint32_t expected = kCacheEmpty;
+            __hip_atomic_compare_exchange_strong(&keys[h], &expected, (uint32_t)g, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            k = expected == kCacheEmpty ? (uint32_t)g : expected;
+        }
+        if (k == (uint32_t)g) {
+            if (W) {
+                double *v = reinterpret_cast<double *>(keys + A.cache_slots);
+                lds_add_f64(&v[2 * h], w);
+                lds_add_f64(&v[2 * h + 1], w * w);
+            } else {
+                lds_add_u32(&keys[A.cache_slots + h], 1u);
+            }
+            return;
+        }
+    }
+    if (W) {
+        gl_add_f64(&A.sumw[g], w);
+        gl_add_f64(&A.sumw2[g], w * w);
+    } else {
+        gl_add_u64(&A.cnt[g], 1ull);
+    }
+}
+
+template <bool W>
+__device__ __forceinline__ void cache_init(const FillArgs &A, char *smem)
+{
+    if (A.lds_cache < 0)
+        return;
+    uint32_t *keys = reinterpret_cast<uint32_t *>(smem + A.lds_cache);
+    const int vwords = A.cache_slots * (W ? 4 : 1);
+    for (int i = threadIdx.x; i < A.cache_slots; i += blockDim.x)
+        keys[i] = kCacheEmpty;
+    for (int i = threadIdx.x; i < vwords; i += blockDim.x)
+        keys[A.cache_slots + i] = 0u;
+}
+
+template <bool W>
+__device__ __forceinline__ void cache_flush(const FillArgs &A, char *smem)
+{
+    if (A.lds_cache < 0)
+        return;
+    const uint32_t *keys = reinterpret_cast<const uint32_t *>(smem + A.lds_cache);
+    for (int i = threadIdx.x; i < A.cache_slots; i += blockDim.x) {
+        const uint32_t k = keys[i];
+        if (k == kCacheEmpty)
+            continue;
+        if (W) {
+            const double *v = reinterpret_cast<const double *>(keys + A.cache_slots);
+            gl_add_f64(&A.sumw[k], v[2 * i]);
+            gl_add_f64(&A.sumw2[k], v[2 * i + 1]);
+        } else {
+            gl_add_u64(&A.cnt[k], keys[A.cache_slots + i]);
+        }
+    }
+}
+
 // Coalesced streaming loads of U events per thread: event base + j*blockDim +
 // tid of the block's range, addressed as 32-bit offsets from the block's
 // (wave-uniform) column pointers; CHECK predicates each load on the block's
@@ -164,7 +234,7 @@ __device__ __forceinline__ void load_batch(const T *const (&xb)[D], const T *wb,
 // Find bin, statistics and accumulation for the U loaded events of a thread
 // (events at offsets >= len are skipped).
 template <int D, typename T, int ACC, bool W, int U, int KS>
-__device__ __forceinline__ void process_batch(const FillArgs &A, const char *smem, uint32_t *win,
+__device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uint32_t *win,
                                               const T (&cx)[U][D], const T (&cw)[U],
                                               uint32_t base, uint32_t len, int cp,
                                               double (&st)[NStats<D>::v])
@@ -179,8 +249,14 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, const char *sme
             x[a][j] = (double)cx[j][a];
         axis_bins<U, kind_of_set<KS>()>(x[a], A.ax[a], smem, b[a]);
     }
+    // compensated FP32: returning LDS adds of the whole batch are issued
+    // before any of their results is used, so their latencies overlap
+    float o1[U], o2[U], wfv[U], w2v[U], e2v[U];
+    uint32_t fidx[U];
+    bool fin[U];
 #pragma unroll
     for (int j = 0; j < U; ++j) {
+        fin[j] = false;
         if (base + (uint32_t)j * blockDim.x + threadIdx.x >= len)
             continue;
         int32_t g = 0;
@@ -212,19 +288,27 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, const char *sme
                 const uint32_t idx = l * A.copies + cp;
                 const float wf = (float)cw[j];
                 const float w2 = wf * wf;
-                const float e2 = __builtin_fmaf(wf, wf, -w2);   // exact: wf*wf = w2 + e2
-                const float o1 = lds_add_rtn_f32(&s[idx], wf);
-                const float c1 = two_sum_err(o1, wf);
-                const float o2 = lds_add_rtn_f32(&s[2 * n1 + idx], w2);
-                const float c2 = two_sum_err(o2, w2) + e2;
-                lds_add_f32(&s[n1 + idx], c1);
-                lds_add_f32(&s[3 * n1 + idx], c2);
+                wfv[j] = wf;
+                w2v[j] = w2;
+                e2v[j] = __builtin_fmaf(wf, wf, -w2);   // exact: wf*wf = w2 + e2
+                fidx[j] = idx;
+                fin[j] = true;
+                o1[j] = lds_add_rtn_f32(&s[idx], wf);
+                o2[j] = lds_add_rtn_f32(&s[2 * n1 + idx], w2);
             }
-        } else if (W) {
-            gl_add_f64(&A.sumw[g], w);
-            gl_add_f64(&A.sumw2[g], w * w);
         } else {
-            gl_add_u64(&A.cnt[g], 1ull);
+            spill<W>(A, smem, g, w);
+        }
+    }
+    if (ACC == ACC_F32C) {
+        float *s = reinterpret_cast<float *>(win);
+        const uint32_t n1 = wlen * A.copies;
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (fin[j]) {
+                lds_add_f32(&s[n1 + fidx[j]], two_sum_err(o1[j], wfv[j]));
+                lds_add_f32(&s[3 * n1 + fidx[j]], two_sum_err(o2[j], w2v[j]) + e2v[j]);
+            }
         }
     }
 }
@@ -242,6 +326,7 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
     const int words = window_words(ACC, A.win_len, A.copies);
     for (int i = tid; i < words; i += nthr)
         win[i] = 0u;
+    cache_init<W>(A, smem);
     __syncthreads();
 
     double st[NS];
@@ -294,6 +379,7 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
     __syncthreads();
     reduce_stats<NS>(st, reinterpret_cast<double *>(smem), A.stats);
     merge_window<ACC>(win, A);
+    cache_flush<W>(A, smem);
 }
 
 // Sums the staging slots of `nblocks` fill workgroups into the histogram.

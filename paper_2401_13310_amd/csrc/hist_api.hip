@@ -392,6 +392,8 @@ FillArgs hg::base_args(const hist_s *h, const void *const *coords, const void *w
     a.w = w;
     a.n = n;
     a.copies = 1;
+    a.lds_cache = -1;
+    a.cache_slots = 0;
     a.cnt = h->d_cnt;
     a.sumw = h->d_sumw;
     a.sumw2 = h->d_sumw2;
@@ -414,6 +416,9 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
             return st;
         a.gbins = h->d_gbins;
         const size_t esz = f32 ? 4 : 8;
+        const int t0 = h->timing ? timing_event(h) : -1;
+        if (t0 >= 0)
+            HIPCHK(hipEventRecord(h->ev_pool[t0], s), "timing event");
         for (int64_t off = 0; off < n; off += cap) {
             const int64_t m = (n - off) < cap ? (n - off) : cap;
             FillArgs c = a;
@@ -453,6 +458,11 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
             t.per_block = per;
             HIPCHK(launch_tile(p.acc, f32, p.threads, bx, tiles, (size_t)p.lds, t, s), "tile launch");
         }
+        const int t1 = h->timing ? timing_event(h) : -1;
+        if (t0 >= 0 && t1 >= 0) {
+            HIPCHK(hipEventRecord(h->ev_pool[t1], s), "timing event");
+            h->ev_fill.emplace_back(t0, t1);
+        }
         return HIST_OK;
     }
     a.win_lo = p.win_lo;
@@ -460,6 +470,8 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
     a.copies = p.copies;
     a.merge = p.merge;
     a.lds_win = p.lds_base;
+    a.lds_cache = p.lds_cache;
+    a.cache_slots = p.cache_slots;
     a.epoch_iters = p.epoch_iters;
     a.per_block = p.per_block;
     if (p.merge == MERGE_STAGE) {

@@ -17,6 +17,14 @@ enum Acc : int32_t {
 
 enum Merge : int32_t { MERGE_ATOMIC = 0, MERGE_STAGE = 1 };
 
+// Out-of-window hot-bin cache: keys (u32) then values (u32 counts, or binary64
+// sum and sum of squares per entry).
+constexpr uint32_t kCacheEmpty = 0xFFFFFFFFu;
+__host__ __device__ inline int cache_bytes(int slots, bool weighted)
+{
+    return slots * 4 + slots * (weighted ? 16 : 4);
+}
+
 // Bytes one bin needs in LDS for one copy.
 __host__ __device__ inline int acc_bytes(int acc)
 {
@@ -51,6 +59,8 @@ struct FillArgs {
     int32_t merge;            // Merge
     int32_t lds_win;          // byte offset of the window arrays in LDS
     int32_t epoch_iters;      // U16: loop iterations between drains
+    int32_t lds_cache;        // byte offset of the out-of-window hot-bin cache, -1: none
+    int32_t cache_slots;      // entries of that cache (power of two)
     uint64_t *cnt;            // [T] unit-weight counts
     double *sumw, *sumw2;     // [T] weighted sums
     double *stats;            // [S]

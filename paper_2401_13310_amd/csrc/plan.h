@@ -25,8 +25,10 @@ struct Plan {
     int merge = MERGE_ATOMIC;
     int64_t per_block = 0;
     int epoch_iters = 1;
-    int lds_base = 0;                // bytes before the window (statistics + models)
+    int lds_base = 0;                // bytes before the window (statistics, models, cache)
     int lds = 0;                     // dynamic LDS bytes per workgroup
+    int lds_cache = -1;              // out-of-window hot-bin cache offset, -1: none
+    int cache_slots = 0;
 };
 
 // Choices the autotuner (or a test) fixes for a shape; 0 / -1 mean "heuristic".

@@ -121,7 +121,14 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
         p.acc = acc;
         int64_t lo = 0, len = h->T;
         if (h->T > cap) {
-            len = cap;
+            // events outside the window: keep a small LDS cache of hot bins
+            constexpr int kSlots = 256;
+            p.lds_cache = base;
+            p.cache_slots = kSlots;
+            p.lds_base = (base + cache_bytes(kSlots, weighted) + 15) & ~15;
+            const int avail2 = h->lds_max - p.lds_base;
+            const int64_t cap2 = acc == ACC_U16 ? (int64_t)(avail2 / 4) * 2 : avail2 / acc_bytes(acc);
+            len = cap2;
             lo = c.win_lo >= 0 ? c.win_lo : 0;
             if (lo + len > h->T)
                 lo = h->T - len;
@@ -136,11 +143,11 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
                 const int64_t fit = avail / std::max<int64_t>(1, len * acc_bytes(acc));
                 copies = (int)std::min<int64_t>(64, std::max<int64_t>(1, fit));
             }
-            while (copies > 1 && window_bytes(acc, len, copies) > avail)
+            while (copies > 1 && window_bytes(acc, len, copies) > h->lds_max - p.lds_base)
                 --copies;
         }
         p.copies = copies;
-        p.lds = base + window_bytes(acc, len, copies);
+        p.lds = p.lds_base + window_bytes(acc, len, copies);
     }
 
     const int U = fill_unroll(h->dims, f32, weighted);
