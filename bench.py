@@ -156,11 +156,24 @@ def load_traffic(path, workload, n):
     return rec.get("bytes_per_launch")
 
 
-def _counter_per_dispatch(db_path, counter):
-    """{kernel name: [value per dispatch]} for one counter of a rocpd database."""
-    import sqlite3
-    db = sqlite3.connect(db_path)
+def _counter_per_dispatch(path, counter):
+    """{kernel name: [value per dispatch]} for one counter, from rocprofv3's
+    counter_collection.csv or its rocpd database."""
     per = {}
+    if path.endswith(".csv"):
+        import csv
+        sums = {}
+        with open(path, newline="") as f:
+            for row in csv.DictReader(f):
+                if row.get("Counter_Name") != counter:
+                    continue
+                key = (int(row["Dispatch_Id"]), row["Kernel_Name"])
+                sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
+        for (disp, kname), val in sorted(sums.items()):
+            per.setdefault(kname, []).append(val)
+        return per
+    import sqlite3
+    db = sqlite3.connect(path)
     for disp, kname, val in db.execute(
             "select dispatch_id, kernel_name, sum(value) from counters_collection "
             "where counter_name = ? group by dispatch_id, kernel_name order by dispatch_id",
@@ -173,6 +186,7 @@ def ingest(args):
     fetch = _counter_per_dispatch(args.ingest[0], "FETCH_SIZE")
     write = _counter_per_dispatch(args.ingest[1], "WRITE_SIZE")
     copy = [k for k in fetch if "copy" in k.lower() and "hg::" not in k]
+    copy += [k for k in fetch if "elementwise" in k.lower() and "hg::" not in k]
     fill = [k for k in fetch if "fill_kernel" in k]
     if not copy or not fill:
         raise SystemExit("ingest: need the fill kernel and the calibration copy in both runs")
@@ -324,7 +338,9 @@ def main():
         torch.cuda.synchronize()
         dst = torch.empty_like(cols[0])
         for _ in range(3):
-            dst.copy_(cols[0])
+            dst.copy_(cols[0])                 # reads and writes n * itemsize bytes
+        for _ in range(3):
+            torch.mul(cols[0], 1.0, out=dst)   # the same traffic, as a plain kernel
         torch.cuda.synchronize()
         print("profile run: %d fills of %d events, plan %s; copy of %d bytes x3; sources %s"
               % (args.steps, n, plan, cols[0].numel() * cols[0].element_size(),

@@ -87,8 +87,14 @@ typedef enum {
     HIST_STRAT_LDS = 1,     /* LDS-privatized window of bins, out-of-window events use
                                global atomics                                          */
     HIST_STRAT_GLOBAL = 2,  /* global atomics only                                     */
-    HIST_STRAT_TILED = 3    /* bins computed once into a scratch array, then bin-range
+    HIST_STRAT_TILED = 3,   /* bins computed once into a scratch array, then bin-range
                                tiles accumulated in LDS                                */
+    HIST_STRAT_PART = 4     /* bins computed once into a scratch array, events then
+                               partitioned by bin range (a counting sort) so that one
+                               workgroup accumulates each range in LDS and owns its
+                               bins: no atomics on the histogram.  For histograms far
+                               larger than LDS (about 1e5 bins and up).  Weights are
+                               accumulated in FP64, also for HIST_F_ACC_F32C.          */
 } hist_strategy;
 
 /* Search used on a variable axis. */

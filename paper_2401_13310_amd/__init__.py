@@ -14,7 +14,7 @@ import numpy as np
 
 from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_LEARNED,
                    HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED, HIST_STRAT_AUTO, HIST_STRAT_GLOBAL,
-                   HIST_STRAT_LDS, HIST_STRAT_TILED, STRAT_NAMES, HistAxis, HistError,
+                   HIST_STRAT_LDS, HIST_STRAT_PART, HIST_STRAT_TILED, STRAT_NAMES, HistAxis, HistError,
                    HistFillDesc, check, load)
 
 __all__ = [
@@ -24,7 +24,7 @@ __all__ = [
     "hist_timing", "hist_timing_read", "hist_set_threads",
     "hist_batch_create", "hist_batch_launch", "hist_batch_launch_eager", "hist_batch_destroy",
     "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_STRAT_AUTO",
-    "HIST_STRAT_LDS", "HIST_STRAT_GLOBAL", "HIST_STRAT_TILED", "HIST_SEARCH_BINARY",
+    "HIST_STRAT_LDS", "HIST_STRAT_GLOBAL", "HIST_STRAT_TILED", "HIST_STRAT_PART", "HIST_SEARCH_BINARY",
     "HIST_SEARCH_LEARNED", "Batch",
 ]
 

@@ -18,10 +18,10 @@ HIST_OK, HIST_EINVAL, HIST_ENOMEM, HIST_EDEVICE, HIST_ECAPTURE, HIST_ENOTSUP = r
 HIST_F64, HIST_F32 = 0, 1
 HIST_F_ACC_F32C = 1 << 0
 HIST_F_LEARNED = 1 << 1
-HIST_STRAT_AUTO, HIST_STRAT_LDS, HIST_STRAT_GLOBAL, HIST_STRAT_TILED = range(4)
+HIST_STRAT_AUTO, HIST_STRAT_LDS, HIST_STRAT_GLOBAL, HIST_STRAT_TILED, HIST_STRAT_PART = range(5)
 HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED = 0, 1
 ACC_NAMES = {0: "u32", 1: "u16", 2: "f64", 3: "f32c"}
-STRAT_NAMES = {0: "auto", 1: "lds", 2: "global", 3: "tiled"}
+STRAT_NAMES = {0: "auto", 1: "lds", 2: "global", 3: "tiled", 4: "part"}
 
 
 class HistAxis(ctypes.Structure):

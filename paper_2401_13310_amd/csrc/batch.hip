@@ -12,7 +12,7 @@
 // copy and statistics with atomics -- tiles of one member run concurrently on
 // several CUs.  The last workgroup to finish resets the queue, so the graph
 // holds a single kernel node and replays need no memset.
-#include "device_common.h"
+#include "part_common.h"
 #include "plan.h"
 
 #include <algorithm>
@@ -22,6 +22,10 @@
 
 namespace hg {
 
+// Member accumulation beyond the LDS accumulators of kernels.h.
+constexpr int kAccGlobal = -1;   // global atomics (histograms too large for LDS, few events)
+constexpr int kAccPart = -2;     // partitioned: count tiles here, then scan, scatter, accumulate
+
 struct MemberDev {
     AxisDev ax[kMaxDims];
     const void *coords[kMaxDims];
@@ -29,14 +33,29 @@ struct MemberDev {
     int64_t n;
     uint64_t *cnt;
     double *sumw, *sumw2, *stats;
-    int32_t dims, f32, acc;       // acc: ACC_U32 / ACC_F64, or -1 for global atomics only
+    int32_t dims, f32, acc;       // acc: ACC_U32 / ACC_F64, kAccGlobal or kAccPart
     int32_t win_len, copies, pad;
+    // kAccPart members: scratch owned by the batch (partition.hip's layout)
+    int32_t *gbins;               // [n] global bin of every event
+    uint16_t *rec_off;            // [n] in-bucket offsets in bucket order
+    double *rec_w;                // [n] weights in bucket order (weighted members)
+    uint32_t *table;              // [nbuckets * ntiles]
+    uint32_t *bucket_start;       // [nbuckets + 1]
+    int64_t T;
+    int32_t nbuckets, bshift, ntiles, pad2;
 };
 
 struct TileDev {
     int64_t start;
     int32_t len;
     int32_t member;
+    int32_t ptile;                // kAccPart members: index of the tile within the member
+    int32_t pad;
+};
+
+struct BucketDev {
+    int32_t member;
+    int32_t bucket;
 };
 
 // Events [start, start+len) of member M: find bin, statistics, accumulation.
@@ -99,6 +118,32 @@ __device__ void batch_events(const MemberDev &M, int64_t start, int32_t len, con
     }
 }
 
+// Count pass of a kAccPart member's tile: global bins to the member's scratch,
+// statistics, and the tile's events per bucket in LDS (`cnt`).
+template <bool F32, bool W>
+__device__ void batch_count_events(const MemberDev &M, int64_t start, int32_t len, const char *smem,
+                                   uint32_t *cnt, double (&st)[kMaxStats])
+{
+    using T = typename std::conditional<F32, float, double>::type;
+    const int dims = M.dims;
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    for (int32_t i = tid; i < len; i += nthr) {
+        double x[kMaxDims] = {0.0, 0.0, 0.0};
+        int32_t g = 0;
+        bool inside = true;
+        for (int a = 0; a < dims; ++a) {
+            x[a] = (double)__builtin_nontemporal_load(static_cast<const T *>(M.coords[a]) + start + i);
+            const int32_t b = axis_bin(x[a], M.ax[a], smem);
+            inside = inside && (uint32_t)(b - 1) < (uint32_t)M.ax[a].nbins;
+            g += (a == 0) ? b : b * M.ax[a].stride;
+        }
+        M.gbins[start + i] = g;
+        if (inside)
+            stats_add_rt(st, x, W ? (double)static_cast<const T *>(M.w)[start + i] : 1.0, dims);
+        lds_add_u32(&cnt[(uint32_t)g >> M.bshift], 1u);
+    }
+}
+
 __global__ void __launch_bounds__(kMaxThreads)
 batch_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ tiles, int ntiles,
              uint32_t *queue, int lds_win)
@@ -126,7 +171,9 @@ batch_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ 
                     dst[i] = src[i];
             }
         }
-        const int words = M.acc < 0 ? 0 : (M.acc == ACC_U32 ? M.win_len * M.copies : M.win_len * M.copies * 4);
+        const int words = M.acc == kAccPart
+                              ? M.nbuckets
+                              : (M.acc < 0 ? 0 : (M.acc == ACC_U32 ? M.win_len * M.copies : M.win_len * M.copies * 4));
         for (int i = tid; i < words; i += nthr)
             win[i] = 0u;
         __syncthreads();
@@ -134,7 +181,19 @@ batch_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ 
         for (int k = 0; k < kMaxStats; ++k)
             st[k] = 0.0;
         const bool weighted = M.w != nullptr;
-        if (M.f32) {
+        if (M.acc == kAccPart) {
+            if (M.f32) {
+                if (weighted)
+                    batch_count_events<true, true>(M, tile.start, tile.len, smem, win, st);
+                else
+                    batch_count_events<true, false>(M, tile.start, tile.len, smem, win, st);
+            } else {
+                if (weighted)
+                    batch_count_events<false, true>(M, tile.start, tile.len, smem, win, st);
+                else
+                    batch_count_events<false, false>(M, tile.start, tile.len, smem, win, st);
+            }
+        } else if (M.f32) {
             if (weighted)
                 batch_events<true, true>(M, tile.start, tile.len, smem, win, st);
             else
@@ -147,8 +206,11 @@ batch_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ 
         }
         __syncthreads();
         reduce_stats<kMaxStats>(st, reinterpret_cast<double *>(smem), M.stats);
-        // merge the LDS copy
-        if (M.acc == ACC_U32) {
+        // merge the LDS copy (kAccPart: store the tile's bucket counts)
+        if (M.acc == kAccPart) {
+            for (int j = tid; j < M.nbuckets; j += nthr)
+                M.table[(int64_t)j * M.ntiles + tile.ptile] = win[j];
+        } else if (M.acc == ACC_U32) {
             for (int l = tid; l < M.win_len; l += nthr) {
                 uint32_t c = 0;
                 for (int r = 0; r < M.copies; ++r)
@@ -184,6 +246,51 @@ batch_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ 
     }
 }
 
+// Scan, scatter and accumulate passes over the kAccPart members of a batch
+// (one workgroup per member, per member tile, per member bucket).
+__global__ void __launch_bounds__(1024)
+batch_part_scan_kernel(const MemberDev *__restrict__ members, const int32_t *__restrict__ part_members)
+{
+    const MemberDev &M = members[part_members[blockIdx.x]];
+    part_scan(M.table, M.bucket_start, M.nbuckets, M.ntiles);
+}
+
+__global__ void __launch_bounds__(kMaxThreads)
+batch_part_scatter_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ ptiles)
+{
+    extern __shared__ __align__(16) char smem[];
+    const TileDev tile = ptiles[blockIdx.x];
+    const MemberDev &M = members[tile.member];
+    uint32_t *cur = reinterpret_cast<uint32_t *>(smem);
+    const int64_t end = tile.start + tile.len;
+    if (!M.w)
+        part_scatter<double, false>(M.gbins, nullptr, tile.start, end, M.table, M.ntiles, tile.ptile,
+                                    M.nbuckets, M.bshift, M.rec_off, M.rec_w, cur);
+    else if (M.f32)
+        part_scatter<float, true>(M.gbins, static_cast<const float *>(M.w), tile.start, end, M.table,
+                                  M.ntiles, tile.ptile, M.nbuckets, M.bshift, M.rec_off, M.rec_w, cur);
+    else
+        part_scatter<double, true>(M.gbins, static_cast<const double *>(M.w), tile.start, end,
+                                   M.table, M.ntiles, tile.ptile, M.nbuckets, M.bshift, M.rec_off,
+                                   M.rec_w, cur);
+}
+
+__global__ void __launch_bounds__(1024)
+batch_part_accum_kernel(const MemberDev *__restrict__ members, const BucketDev *__restrict__ buckets)
+{
+    extern __shared__ __align__(16) char smem[];
+    const BucketDev bk = buckets[blockIdx.x];
+    const MemberDev &M = members[bk.member];
+    const int64_t g0 = (int64_t)bk.bucket << M.bshift;
+    const int64_t bw = (int64_t)1 << M.bshift;
+    const int len = (int)((M.T - g0) < bw ? (M.T - g0) : bw);
+    const uint32_t r0 = M.bucket_start[bk.bucket], r1 = M.bucket_start[bk.bucket + 1];
+    if (M.w)
+        part_accum<true>(M.rec_off, M.rec_w, r0, r1, g0, len, M.cnt, M.sumw, M.sumw2, smem);
+    else
+        part_accum<false>(M.rec_off, M.rec_w, r0, r1, g0, len, M.cnt, M.sumw, M.sumw2, smem);
+}
+
 __global__ void zero_u32_kernel(uint32_t *p, int n)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -204,6 +311,13 @@ struct hist_batch_s {
     int ntiles = 0;
     int blocks = 1, threads = 1024;
     int lds = 0, lds_win = 0;
+    // partitioned members
+    int npart = 0, nptiles = 0, nbuckets = 0;
+    int32_t *d_part_members = nullptr;
+    TileDev *d_ptiles = nullptr;
+    BucketDev *d_buckets = nullptr;
+    void *d_part = nullptr;
+    int scatter_lds = 0, accum_lds = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -225,6 +339,14 @@ static void batch_free(hist_batch_s *b)
         (void)hipFree(b->d_tiles);
     if (b->d_queue)
         (void)hipFree(b->d_queue);
+    if (b->d_part_members)
+        (void)hipFree(b->d_part_members);
+    if (b->d_ptiles)
+        (void)hipFree(b->d_ptiles);
+    if (b->d_buckets)
+        (void)hipFree(b->d_buckets);
+    if (b->d_part)
+        (void)hipFree(b->d_part);
     delete b;
 }
 
@@ -232,6 +354,15 @@ static hipError_t batch_enqueue(hist_batch_s *b, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_kernel, dim3(b->blocks), dim3(b->threads), (size_t)b->lds, s,
                        b->d_members, b->d_tiles, b->ntiles, b->d_queue, b->lds_win);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || b->npart == 0)
+        return e;
+    hipLaunchKernelGGL(batch_part_scan_kernel, dim3(b->npart), dim3(1024), 0, s, b->d_members,
+                       b->d_part_members);
+    hipLaunchKernelGGL(batch_part_scatter_kernel, dim3(b->nptiles), dim3(1024), (size_t)b->scatter_lds,
+                       s, b->d_members, b->d_ptiles);
+    hipLaunchKernelGGL(batch_part_accum_kernel, dim3(b->nbuckets), dim3(1024), (size_t)b->accum_lds,
+                       s, b->d_members, b->d_buckets);
     return hipGetLastError();
 }
 
@@ -284,7 +415,13 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     const int avail = h0->lds_max - b->lds_win - 64;   // room for the kernel's static LDS
 
     std::vector<MemberDev> mem((size_t)k);
-    std::vector<TileDev> tiles;
+    std::vector<TileDev> tiles, ptiles;
+    std::vector<int32_t> part_members;
+    std::vector<BucketDev> buckets;
+    std::vector<size_t> part_off((size_t)k, 0);   // scratch offsets of kAccPart members
+    size_t part_bytes = 0;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    constexpr int64_t kPartTile = 65536;          // events per count / scatter tile
     int max_window_bytes = 0;
     for (int i = 0; i < k; ++i) {
         hist_s *h = hs[i];
@@ -311,17 +448,49 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         m.dims = h->dims;
         m.f32 = d.dtype == HIST_F32 ? 1 : 0;
         const int bytes = d.weights ? 16 : 4;
+        m.T = h->T;
+        m.copies = 1;
+        // bucket width of a partitioned member: the bucket fits LDS in the
+        // accumulate pass, the bucket counters fit the window room
+        int pbits = d.weights ? 12 : 13;
+        while (pbits < 16 && ((h->T + ((int64_t)1 << pbits) - 1) >> pbits) * 4 > avail)
+            ++pbits;
+        const int64_t pnb = (h->T + ((int64_t)1 << pbits) - 1) >> pbits;
+        const bool part_ok = ((int64_t)bytes << pbits) <= h0->lds_max && pnb * 4 <= avail;
         if (h->T * bytes <= avail) {
             m.acc = d.weights ? ACC_F64 : ACC_U32;
             m.win_len = (int32_t)h->T;
-            m.copies = 1;
             max_window_bytes = std::max(max_window_bytes, (int)(h->T * bytes));
+        } else if (part_ok && d.n >= kPartTile) {
+            m.acc = kAccPart;
+            m.bshift = pbits;
+            m.nbuckets = (int32_t)pnb;
+            m.ntiles = (int32_t)((d.n + kPartTile - 1) / kPartTile);
+            max_window_bytes = std::max(max_window_bytes, (int)(pnb * 4));
+            b->scatter_lds = std::max(b->scatter_lds, (int)(pnb * 4));
+            b->accum_lds = std::max(b->accum_lds, bytes << pbits);
+            part_off[(size_t)i] = part_bytes;
+            part_bytes += up((size_t)d.n * 4) + up((size_t)d.n * 2) +
+                          (d.weights ? up((size_t)d.n * 8) : 0) +
+                          up((size_t)pnb * m.ntiles * 4) + up((size_t)(pnb + 1) * 4);
+            part_members.push_back(i);
+            for (int64_t j = 0; j < pnb; ++j)
+                buckets.push_back(BucketDev{i, (int32_t)j});
         } else {
-            m.acc = -1;
+            m.acc = kAccGlobal;
             m.win_len = 0;
-            m.copies = 1;
         }
         b->n.push_back(d.n);
+        if (m.acc == kAccPart) {
+            for (int32_t t = 0; t < m.ntiles; ++t) {
+                const int64_t s0 = (int64_t)t * kPartTile;
+                const int64_t s1 = std::min<int64_t>(d.n, s0 + kPartTile);
+                const TileDev td{s0, (int32_t)(s1 - s0), i, t, 0};
+                tiles.push_back(td);
+                ptiles.push_back(td);
+            }
+            continue;
+        }
         // tiles: LDS members get enough events per tile to amortize the
         // zeroing and merging of their window
         const int64_t tile_len = m.acc >= 0 ? std::max<int64_t>(65536, 32 * (int64_t)m.win_len) : 131072;
@@ -329,9 +498,12 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         for (int64_t t = 0; t < nt; ++t) {
             const int64_t s0 = d.n * t / nt, s1 = d.n * (t + 1) / nt;
             if (s1 > s0)
-                tiles.push_back(TileDev{s0, (int32_t)(s1 - s0), i});
+                tiles.push_back(TileDev{s0, (int32_t)(s1 - s0), i, 0, 0});
         }
     }
+    b->npart = (int)part_members.size();
+    b->nptiles = (int)ptiles.size();
+    b->nbuckets = (int)buckets.size();
     std::stable_sort(tiles.begin(), tiles.end(),
                      [](const TileDev &x, const TileDev &y) { return x.len > y.len; });
     b->ntiles = (int)tiles.size();
@@ -340,7 +512,51 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     const int bpc = b->lds * 2 <= h0->lds_max ? 2 : 1;
     b->blocks = std::max(1, std::min(h0->num_cu * bpc, std::max(1, b->ntiles)));
 
-    hipError_t e = hipMalloc(&b->d_members, sizeof(MemberDev) * (size_t)k);
+    hipError_t e = hipSuccess;
+    if (b->npart > 0) {
+        e = hipMalloc(&b->d_part, part_bytes);
+        if (e == hipSuccess)
+            e = hipMalloc(&b->d_part_members, sizeof(int32_t) * part_members.size());
+        if (e == hipSuccess)
+            e = hipMalloc(&b->d_ptiles, sizeof(TileDev) * ptiles.size());
+        if (e == hipSuccess)
+            e = hipMalloc(&b->d_buckets, sizeof(BucketDev) * buckets.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_part_members, part_members.data(), sizeof(int32_t) * part_members.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_ptiles, ptiles.data(), sizeof(TileDev) * ptiles.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->d_buckets, buckets.data(), sizeof(BucketDev) * buckets.size(),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            for (int i : part_members) {
+                MemberDev &m = mem[(size_t)i];
+                const size_t nn = (size_t)m.n;
+                char *q = static_cast<char *>(b->d_part) + part_off[(size_t)i];
+                m.gbins = reinterpret_cast<int32_t *>(q);
+                q += up(nn * 4);
+                m.rec_off = reinterpret_cast<uint16_t *>(q);
+                q += up(nn * 2);
+                if (m.w) {
+                    m.rec_w = reinterpret_cast<double *>(q);
+                    q += up(nn * 8);
+                }
+                m.table = reinterpret_cast<uint32_t *>(q);
+                q += up((size_t)m.nbuckets * m.ntiles * 4);
+                m.bucket_start = reinterpret_cast<uint32_t *>(q);
+            }
+        }
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(batch_part_scatter_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, h0->lds_max);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(batch_part_accum_kernel),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, h0->lds_max);
+    }
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_members, sizeof(MemberDev) * (size_t)k);
     if (e == hipSuccess)
         e = hipMalloc(&b->d_tiles, sizeof(TileDev) * std::max<size_t>(1, tiles.size()));
     if (e == hipSuccess)

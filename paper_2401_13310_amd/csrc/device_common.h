@@ -70,6 +70,23 @@ __device__ __forceinline__ void stats_add(double (&st)[NStats<D>::v], const doub
     }
 }
 
+// The same terms for unit weights, except w and w*w (the caller counts the
+// events): w*x = x and (w*x)*x = x*x exactly.
+template <int D>
+__device__ __forceinline__ void stats_add_unit(double (&st)[NStats<D>::v], const double (&x)[D])
+{
+#pragma clang fp contract(off)
+    int k = 2;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        st[k++] += x[a];
+        st[k++] += x[a] * x[a];
+#pragma unroll
+        for (int c = 0; c < a; ++c)
+            st[k++] += x[c] * x[a];
+    }
+}
+
 // Block reduction of the statistics partials, then one binary64 atomic per
 // statistic per workgroup (sums accumulate across fills).
 template <int NS>

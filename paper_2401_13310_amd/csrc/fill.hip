@@ -26,21 +26,6 @@
 
 namespace hg {
 
-template <int D>
-__device__ __forceinline__ void stage_models(const AxisDev (&ax)[kMaxDims], char *smem)
-{
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (ax[a].kind == AX_LEARNED && ax[a].lds_model >= 0) {
-            const double *src = reinterpret_cast<const double *>(ax[a].model);
-            double *dst = reinterpret_cast<double *>(smem + ax[a].lds_model);
-            const int nd = ax[a].nseg * (int)(sizeof(ModelSeg) / sizeof(double));
-            for (int i = threadIdx.x; i < nd; i += blockDim.x)
-                dst[i] = src[i];
-        }
-    }
-}
-
 // 32-bit words of the LDS window arrays.
 __device__ __forceinline__ int window_words(int acc, int win_len, int copies)
 {
@@ -211,54 +196,72 @@ __device__ __forceinline__ void cache_flush(const FillArgs &A, char *smem)
 
 // Coalesced streaming loads of U events per thread: event base + j*blockDim +
 // tid of the block's range, addressed as 32-bit offsets from the block's
-// (wave-uniform) column pointers; CHECK predicates each load on the block's
-// length.  Non-temporal, so the event stream does not evict edges and models.
-template <int D, typename T, bool W, int U, bool CHECK>
+// (wave-uniform) column pointers.  Offsets past the block's length (len >= 1)
+// load the last event instead; process_batch skips them.  Every load is issued
+// unconditionally, so the waits for loads issued before these stay exact.
+// Non-temporal, so the event stream does not evict edges and models.
+template <int D, typename T, bool W, int U>
 __device__ __forceinline__ void load_batch(const T *const (&xb)[D], const T *wb, uint32_t base,
                                            uint32_t len, T (&x)[U][D], T (&w)[U])
 {
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         const uint32_t i = base + (uint32_t)j * blockDim.x + threadIdx.x;
-        const bool ok = !CHECK || i < len;
+        const uint32_t ic = i < len ? i : len - 1;
 #pragma unroll
         for (int a = 0; a < D; ++a)
-            x[j][a] = ok ? __builtin_nontemporal_load(xb[a] + i) : T(0);
-        if (W)
-            w[j] = ok ? __builtin_nontemporal_load(wb + i) : T(0);
-        else
-            w[j] = T(0);
+            x[j][a] = __builtin_nontemporal_load(xb[a] + ic);
+        w[j] = W ? __builtin_nontemporal_load(wb + ic) : T(0);
     }
 }
 
 // Find bin, statistics and accumulation for the U loaded events of a thread
-// (events at offsets >= len are skipped).
-template <int D, typename T, int ACC, bool W, int U, int KS>
+// (events at offsets >= len are skipped).  `prefetch` issues the loads of the
+// next batch: first thing for fixed-width axes, else once the first edge
+// loads of the searches are issued, so that those, not the next batch, are
+// what the searches wait for.  Unit weights count their in-range events in
+// `nin` (the w and w^2 statistics) instead of adding 1.0 twice.  Events
+// outside the LDS window are handled after the batch's LDS adds, in a branch
+// the wave skips when none of its lanes has one.
+template <int D, typename T, int ACC, bool W, int U, int KS, typename Prefetch>
 __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uint32_t *win,
                                               const T (&cx)[U][D], const T (&cw)[U],
                                               uint32_t base, uint32_t len, int cp,
-                                              double (&st)[NStats<D>::v])
+                                              double (&st)[NStats<D>::v], uint32_t &nin,
+                                              Prefetch &&prefetch)
 {
+    constexpr int KIND = kind_of_set<KS>();
+    constexpr bool early = KIND == AX_UNIFORM;
+    if (early)
+        prefetch();
     const uint32_t wlen = (uint32_t)A.win_len;
     double x[D][U];
-    int32_t b[D][U];
+    int32_t b[D][U], lo[D][U], hi[D][U];
+    double ev[D][U];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
 #pragma unroll
         for (int j = 0; j < U; ++j)
             x[a][j] = (double)cx[j][a];
-        axis_bins<U, kind_of_set<KS>()>(x[a], A.ax[a], smem, b[a]);
+        axis_bins_begin<U, KIND>(x[a], A.ax[a], smem, lo[a], hi[a], ev[a]);
     }
+    if (!early)
+        prefetch();
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        axis_bins_finish<U, KIND>(x[a], A.ax[a], lo[a], hi[a], ev[a], b[a]);
     // compensated FP32: returning LDS adds of the whole batch are issued
     // before any of their results is used, so their latencies overlap
     float o1[U], o2[U], wfv[U], w2v[U], e2v[U];
     uint32_t fidx[U];
     bool fin[U];
+    int32_t gv[U];
+    bool out[U];
+    bool any_out = false;
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         fin[j] = false;
-        if (base + (uint32_t)j * blockDim.x + threadIdx.x >= len)
-            continue;
+        const bool ok = base + (uint32_t)j * blockDim.x + threadIdx.x < len;
         int32_t g = 0;
         bool inside = true;
         double xe[D];
@@ -268,24 +271,33 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
             inside = inside && (uint32_t)(b[a][j] - 1) < (uint32_t)A.ax[a].nbins;
             g += (a == 0) ? b[a][j] : b[a][j] * A.ax[a].stride;
         }
+        gv[j] = g;
         const double w = W ? (double)cw[j] : 1.0;
-        if (inside)
-            stats_add<D>(st, xe, w);
+        if (ok && inside) {
+            if (W) {
+                stats_add<D>(st, xe, w);
+            } else {
+                stats_add_unit<D>(st, xe);
+                ++nin;
+            }
+        }
         const uint32_t l = (uint32_t)(g - A.win_lo);
-        if (l < wlen) {
+        out[j] = ok && !(l < wlen);
+        any_out = any_out || out[j];
+        if (ok && l < wlen) {
             if (ACC == ACC_U32) {
-                lds_add_u32(&win[l * A.copies + cp], 1u);
+                lds_add_u32(&win[__umul24(l, (uint32_t)A.copies) + cp], 1u);
             } else if (ACC == ACC_U16) {
                 lds_add_u32(&win[l >> 1], 1u << ((l & 1u) << 4));
             } else if (ACC == ACC_F64) {
                 double *s = reinterpret_cast<double *>(win);
-                const uint32_t idx = l * A.copies + cp;
+                const uint32_t idx = __umul24(l, (uint32_t)A.copies) + cp;
                 lds_add_f64(&s[idx], w);
                 lds_add_f64(&s[wlen * A.copies + idx], w * w);
             } else {
                 float *s = reinterpret_cast<float *>(win);
                 const uint32_t n1 = wlen * A.copies;
-                const uint32_t idx = l * A.copies + cp;
+                const uint32_t idx = __umul24(l, (uint32_t)A.copies) + cp;
                 const float wf = (float)cw[j];
                 const float w2 = wf * wf;
                 wfv[j] = wf;
@@ -296,8 +308,6 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
                 o1[j] = lds_add_rtn_f32(&s[idx], wf);
                 o2[j] = lds_add_rtn_f32(&s[2 * n1 + idx], w2);
             }
-        } else {
-            spill<W>(A, smem, g, w);
         }
     }
     if (ACC == ACC_F32C) {
@@ -310,6 +320,12 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
                 lds_add_f32(&s[3 * n1 + fidx[j]], two_sum_err(o2[j], w2v[j]) + e2v[j]);
             }
         }
+    }
+    if (any_out) {
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (out[j])
+                spill<W>(A, smem, gv[j], W ? (double)cw[j] : 1.0);
     }
 }
 
@@ -333,6 +349,7 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
 #pragma unroll
     for (int k = 0; k < NS; ++k)
         st[k] = 0.0;
+    uint32_t nin = 0;   // unit weights: in-range events (w and w^2 statistics)
 
     const int64_t start = (int64_t)blockIdx.x * A.per_block;
     const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
@@ -340,28 +357,23 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
     int it = 0;
 
     // Software pipeline: the loads of the next U events per thread are in
-    // flight while the current ones are binned and accumulated.  Full
-    // iterations run without bounds checks; the last one is checked.
+    // flight while the current ones are binned and accumulated (the last
+    // iteration reloads the block's last event, unused).
     const uint32_t len = (uint32_t)(end > start ? end - start : 0);
     const uint32_t step = (uint32_t)nthr * U;
-    const uint32_t nfull = len / step;
     const T *xb[D];
 #pragma unroll
     for (int a = 0; a < D; ++a)
         xb[a] = static_cast<const T *>(A.coords[a]) + start;
     const T *wb = W ? static_cast<const T *>(A.w) + start : nullptr;
     T cx[U][D], cw[U];
-    if (nfull > 0)
-        load_batch<D, T, W, U, false>(xb, wb, 0, len, cx, cw);
-    else
-        load_batch<D, T, W, U, true>(xb, wb, 0, len, cx, cw);
-    for (uint32_t k = 0, base = 0; base < len; ++k, base += step) {
+    if (len > 0)
+        load_batch<D, T, W, U>(xb, wb, 0, len, cx, cw);
+    for (uint32_t base = 0; base < len; base += step) {
         T nx[U][D], nw[U];
-        if (k + 1 < nfull)
-            load_batch<D, T, W, U, false>(xb, wb, base + step, len, nx, nw);
-        else
-            load_batch<D, T, W, U, true>(xb, wb, base + step, len, nx, nw);
-        process_batch<D, T, ACC, W, U, KS>(A, smem, win, cx, cw, base, len, cp, st);
+        process_batch<D, T, ACC, W, U, KS>(A, smem, win, cx, cw, base, len, cp, st, nin, [&] {
+            load_batch<D, T, W, U>(xb, wb, base + step, len, nx, nw);
+        });
         if (ACC == ACC_U16 && ++it == A.epoch_iters) {
             it = 0;
             __syncthreads();
@@ -375,6 +387,10 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
                 cx[j][a] = nx[j][a];
             cw[j] = nw[j];
         }
+    }
+    if (!W) {
+        st[0] = (double)nin;
+        st[1] = (double)nin;
     }
     __syncthreads();
     reduce_stats<NS>(st, reinterpret_cast<double *>(smem), A.stats);
@@ -610,6 +626,8 @@ static void allow_big_lds(K kernel)
     if (done.insert(key).second)
         (void)hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, 163840);
 }
+
+void allow_big_lds_ptr(const void *kernel) { allow_big_lds(kernel); }
 
 template <int D, typename T, int ACC, bool W, int KS>
 static hipError_t launch_fill_t(int threads, int blocks, size_t lds, const FillArgs &a,

@@ -112,6 +112,7 @@ static void free_handle(hist_s *h)
     dfree(h->d_stats);
     dfree(h->d_stage);
     dfree(h->d_gbins);
+    dfree(h->d_part);
     for (hipEvent_t e : h->ev_pool)
         (void)hipEventDestroy(e);
     delete h;
@@ -214,7 +215,7 @@ extern "C" hist_status hist_create(int dims, const hist_axis *axes, uint32_t fla
             d.xmin = ax.xmin;
             d.xmax = ax.xmax;
             d.width = ax.xmax - ax.xmin;
-            d.inv_width = 1.0 / d.width;
+            d.guess = d.nbins_d / d.width;
             d.margin = 1e-15 * ((double)ax.nbins + 1.0);
         }
     }
@@ -300,9 +301,94 @@ hist_status hg::ensure_gbins(hist_s *h, int64_t count, hipStream_t s)
     if (h->d_gbins) {
         (void)hipStreamSynchronize(s);
         dfree(h->d_gbins);
+    dfree(h->d_part);
     }
     h->d_gbins = p;
     h->gbins_cap = count;
+    return HIST_OK;
+}
+
+static hist_status ensure_part(hist_s *h, size_t bytes, hipStream_t s)
+{
+    if (h->part_bytes >= bytes)
+        return HIST_OK;
+    if (is_capturing(s))
+        return set_error(HIST_ECAPTURE, "hist_fill: the partition scratch is not allocated "
+                                        "yet; fill once before capturing");
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess)
+        return set_error(HIST_ENOMEM, "partition scratch of %zu bytes: %s", bytes,
+                         hipGetErrorString(e));
+    if (h->d_part) {
+        (void)hipStreamSynchronize(s);
+        dfree(h->d_part);
+    }
+    h->d_part = p;
+    h->part_bytes = bytes;
+    return HIST_OK;
+}
+
+// The four passes of the partitioned strategy over chunks of at most
+// part_chunk events (see partition.hip).
+static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *const *coords,
+                            const void *w, int64_t n, bool f32, hipStream_t s)
+{
+    const bool weighted = w != nullptr;
+    const int64_t cap = part_chunk(h);
+    const int64_t mmax = n < cap ? n : cap;
+    const int b = p.bucket_bits;
+    const int nb = (int)((h->T + ((int64_t)1 << b) - 1) >> b);
+    const int G = p.blocks;
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t table_b = up((size_t)nb * G * 4), start_b = up((size_t)(nb + 1) * 4);
+    const size_t off_b = up((size_t)mmax * 2), w_b = weighted ? up((size_t)mmax * 8) : 0;
+    hist_status st = ensure_gbins(h, mmax, s);
+    if (st != HIST_OK)
+        return st;
+    st = ensure_part(h, table_b + start_b + off_b + w_b, s);
+    if (st != HIST_OK)
+        return st;
+    char *base = static_cast<char *>(h->d_part);
+    PartArgs P;
+    std::memset(&P, 0, sizeof(P));
+    P.table = reinterpret_cast<uint32_t *>(base);
+    P.bucket_start = reinterpret_cast<uint32_t *>(base + table_b);
+    P.rec_off = reinterpret_cast<uint16_t *>(base + table_b + start_b);
+    P.rec_w = weighted ? reinterpret_cast<double *>(base + table_b + start_b + off_b) : nullptr;
+    P.T = h->T;
+    P.nbuckets = nb;
+    P.bshift = b;
+    P.lds_buckets = p.lds_base;
+    a.gbins = h->d_gbins;
+    const size_t esz = f32 ? 4 : 8;
+    const size_t acc_lds = (size_t)(weighted ? 16 : 4) << b;
+    const int t0 = h->timing ? timing_event(h) : -1;
+    if (t0 >= 0)
+        HIPCHK(hipEventRecord(h->ev_pool[t0], s), "timing event");
+    for (int64_t off = 0; off < n; off += cap) {
+        const int64_t m = (n - off) < cap ? (n - off) : cap;
+        FillArgs c = a;
+        for (int d = 0; d < h->dims; ++d)
+            c.coords[d] = static_cast<const char *>(coords[d]) + off * esz;
+        c.w = w ? static_cast<const char *>(w) + off * esz : nullptr;
+        c.n = m;
+        int64_t per = (m + G - 1) / G;
+        per = (per + p.threads - 1) / p.threads * p.threads;
+        const int g = (int)((m + per - 1) / per);
+        c.per_block = per;
+        HIPCHK(launch_part_count(h->dims, f32, weighted, p.threads, g, (size_t)p.lds, c, P, s),
+               "partition count launch");
+        HIPCHK(launch_part_scan(P, g, s), "partition scan launch");
+        HIPCHK(launch_part_scatter(f32, weighted, p.threads, g, (size_t)p.lds, c, P, s),
+               "partition scatter launch");
+        HIPCHK(launch_part_accum(weighted, 1024, acc_lds, c, P, s), "partition accumulate launch");
+    }
+    const int t1 = h->timing ? timing_event(h) : -1;
+    if (t0 >= 0 && t1 >= 0) {
+        HIPCHK(hipEventRecord(h->ev_pool[t1], s), "timing event");
+        h->ev_fill.emplace_back(t0, t1);
+    }
     return HIST_OK;
 }
 
@@ -409,6 +495,8 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
     const bool weighted = w != nullptr;
     FillArgs a = base_args(h, coords, w, n);
     apply_model_offsets(h, a);
+    if (p.strategy == HIST_STRAT_PART)
+        return run_part(h, p, a, coords, w, n, f32, s);
     if (p.strategy == HIST_STRAT_TILED) {
         const int64_t cap = tiled_chunk(h);
         hist_status st = ensure_gbins(h, n < cap ? n : cap, s);

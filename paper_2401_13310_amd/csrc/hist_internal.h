@@ -24,7 +24,7 @@ enum Feature : int32_t { FEAT_KEY = 0, FEAT_LINEAR = 1 };
 // segment-local feature z, y = af + z (b + c z) is evaluated in FP32 and the
 // bin provably lies in [ai + ceil(y), ai + floor(y + w)].  c and w are stored
 // as IEEE half in cw (c low, w high); the lower-bound offset is folded into af.
-struct ModelSeg {
+struct alignas(16) ModelSeg {
     float af, b;
     int32_t ai;
     uint32_t cw;
@@ -37,7 +37,7 @@ struct AxisDev {
     double xmin, xmax;      // range; variable axes: e[0] and e[nbins]
     double nbins_d;         // (double)nbins
     double width;           // xmax - xmin, rounded once (the formula's denominator)
-    double inv_width;       // 1 / width rounded: only for the guess of the fast path
+    double guess;           // nbins / width rounded: only for the guess of the fast path
     const double *edges;    // device, nbins+1 values (variable axes)
     const ModelSeg *model;  // device, nseg segments (learned)
     int32_t nseg;
@@ -58,30 +58,45 @@ struct AxisDev {
 // --------------------------------------------------------------------------
 // Fixed-width axis.  The result is defined by the binary64 evaluation
 // t = x - xmin, u = nbins * t, v = u / width (each rounded to nearest, no
-// fused multiply-add), bin = 1 + trunc(v) clamped to nbins.  The kernel first
-// guesses v with a multiply by the rounded reciprocal; that guess differs from
-// the correctly rounded quotient by under 3 ulp of v <= nbins, so when its
-// fractional part is farther than `margin` (1e-15 * (nbins + 1), about 9 ulp
-// of nbins) from 0 and from 1, its floor equals floor(v) and the division is
-// skipped.  Otherwise the exact division decides.
+// fused multiply-add), bin = 1 + trunc(v) clamped to nbins.  The kernels first
+// guess v as q = t * guess with guess = nbins / width rounded: q and v each
+// lie within two roundings (relative 2u, u = 2^-53) of the exact nbins t /
+// width, so |q - v| < 4.0001 u nbins, below `margin` = 1e-15 (nbins + 1).
+// When the fractional part of q is farther than margin from 0 and from 1,
+// floor(q) = floor(v) and the division is skipped; otherwise (in practice
+// never, for random data) the exact division decides.  The guess is formed
+// for every coordinate (clamped to stay finite for out-of-range x) without
+// branches, and the division runs only when some lane of the wave needs it.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ int32_t bin_uniform(double x, const AxisDev &ax)
+template <int U>
+__device__ __forceinline__ void bins_uniform(const double (&x)[U], const AxisDev &ax,
+                                             int32_t (&b)[U])
 {
 #pragma clang fp contract(off)
-    if (x < ax.xmin)
-        return 0;
-    if (!(x < ax.xmax))
-        return ax.nbins + 1;
-    const double t = x - ax.xmin;
-    const double u = ax.nbins_d * t;
-    const double q = u * ax.inv_width;
-    const double k = __builtin_floor(q);
-    int32_t b;
-    if (__builtin_fabs((q - k) - 0.5) < 0.5 - ax.margin)
-        b = (int32_t)k + 1;
-    else
-        b = (int32_t)(u / ax.width) + 1;
-    return b < ax.nbins ? b : ax.nbins;
+    double t[U];
+    bool slow[U];
+    bool any_slow = false;
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const bool in = !(x[j] < ax.xmin) && x[j] < ax.xmax;
+        t[j] = x[j] - ax.xmin;
+        const double q = t[j] * ax.guess;
+        const double k = __builtin_floor(q);
+        slow[j] = in && !(__builtin_fabs((q - k) - 0.5) < 0.5 - ax.margin);
+        any_slow = any_slow || slow[j];
+        b[j] = (int32_t)__builtin_fmin(__builtin_fmax(k, 0.0), ax.nbins_d) + 1;
+    }
+    if (__builtin_amdgcn_ballot_w64(any_slow)) {
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            if (slow[j])
+                b[j] = (int32_t)((ax.nbins_d * t[j]) / ax.width) + 1;
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const int32_t v = b[j] < ax.nbins ? b[j] : ax.nbins;
+        b[j] = x[j] < ax.xmin ? 0 : (x[j] < ax.xmax ? v : ax.nbins + 1);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -120,18 +135,52 @@ __device__ __forceinline__ uint32_t key_feature(double x, const AxisDev &ax)
     return k - ax.key0;
 }
 
+__device__ __forceinline__ void key_seg(uint32_t f, const AxisDev &ax, int32_t &s, float &z)
+{
+    const uint32_t sf = f >> ax.kshift;
+    s = (int32_t)(sf < (uint32_t)(ax.nseg - 1) ? sf : (uint32_t)(ax.nseg - 1));
+    z = (float)(f - ((uint32_t)s << ax.kshift)) * ax.zscale;
+}
+
+__device__ __forceinline__ void linear_seg(double x, const AxisDev &ax, int32_t &s, float &z)
+{
+    const double t = (x - ax.x0) * ax.fscale;
+    // the clamp only matters outside [e[0], e[nbins]) (and for NaN): it keeps
+    // the segment index in [0, nseg) for any x
+    const double tc = __builtin_fmin(__builtin_fmax(t, 0.0), (double)(ax.nseg - 1));
+    s = (int32_t)tc;
+    z = (float)(t - (double)s);
+}
+
 __device__ __forceinline__ void seg_and_z(double x, const AxisDev &ax, int32_t &s, float &z)
 {
+    if (ax.feature == FEAT_KEY)
+        key_seg(key_feature(x, ax), ax, s, z);
+    else
+        linear_seg(x, ax, s, z);
+}
+
+// seg_and_z of U coordinates, with the (wave-uniform) choice of feature taken
+// once for the batch.
+template <int U>
+__device__ __forceinline__ void seg_and_z_batch(const double (&x)[U], const AxisDev &ax,
+                                                int32_t (&s)[U], float (&z)[U])
+{
     if (ax.feature == FEAT_KEY) {
-        const uint32_t f = key_feature(x, ax);
-        const uint32_t sf = f >> ax.kshift;
-        s = (int32_t)(sf < (uint32_t)(ax.nseg - 1) ? sf : (uint32_t)(ax.nseg - 1));
-        z = (float)(f - ((uint32_t)s << ax.kshift)) * ax.zscale;
+        if (ax.keypos) {
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                key_seg(((uint32_t)((uint64_t)__double_as_longlong(x[j]) >> 32) | 0x80000000u) - ax.key0,
+                        ax, s[j], z[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                key_seg(order_key32(x[j]) - ax.key0, ax, s[j], z[j]);
+        }
     } else {
-        const double t = (x - ax.x0) * ax.fscale;
-        const int32_t si = (int32_t)t;
-        s = si < ax.nseg - 1 ? si : ax.nseg - 1;
-        z = (float)(t - (double)s);
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            linear_seg(x[j], ax, s[j], z[j]);
     }
 }
 
@@ -151,39 +200,45 @@ __device__ __forceinline__ float model_eval(const ModelSeg &m, float z)
     return __builtin_fmaf(__builtin_fmaf(half_lo(m.cw), z, m.b), z, m.af);
 }
 
-// Candidate interval [lo, hi] of the bin of x on a variable axis from the
-// learned model (from LDS or global memory).  Underflow and overflow give
-// lo = hi = 0 or nbins+1.  The interval always holds the bin (see learned.hip);
-// an empty interval cannot occur for a correctly trained model, and the full
-// range [1, nbins] is searched then.
-__device__ __forceinline__ void learned_interval(double x, const AxisDev &ax,
-                                                 const ModelSeg *__restrict__ model,
-                                                 int32_t &lo, int32_t &hi)
+// Candidate intervals [lo, hi] of the bins of U coordinates on a variable
+// axis from the learned model (in LDS).  Underflow and overflow give lo = hi =
+// 0 or nbins+1.  The interval always holds the bin (see learned.hip); an empty
+// interval cannot occur for a correctly trained model, and the full range
+// [1, nbins] is searched then.  Branch-free: the segment of every coordinate
+// (clamped into the model for out-of-range x) is read before any is used, so
+// the U LDS reads overlap.
+template <int U>
+__device__ __forceinline__ void learned_intervals(const double (&x)[U], const AxisDev &ax,
+                                                  const ModelSeg *__restrict__ model,
+                                                  int32_t (&lo)[U], int32_t (&hi)[U])
 {
-    if (x < ax.xmin) {
-        lo = hi = 0;
-        return;
-    }
-    if (!(x < ax.xmax)) {
-        lo = hi = ax.nbins + 1;
-        return;
-    }
-    int32_t s;
-    float z;
-    seg_and_z(x, ax, s, z);
-    const ModelSeg m = model[s];
-    const float y = model_eval(m, z);
-    // clamp before converting so ai + offset stays in int32 (an infinite width
-    // becomes the whole axis)
-    const float ylo = __builtin_fminf(__builtin_fmaxf(__builtin_ceilf(y), -0x1p30f), 0x1p30f);
-    const float yhi = __builtin_fminf(__builtin_fmaxf(__builtin_floorf(y + half_hi(m.cw)), -0x1p30f), 0x1p30f);
-    const int32_t l = m.ai + (int32_t)ylo;
-    const int32_t h = m.ai + (int32_t)yhi;
-    lo = l < 1 ? 1 : (l > ax.nbins ? ax.nbins : l);
-    hi = h < 1 ? 1 : (h > ax.nbins ? ax.nbins : h);
-    if (lo > hi) {
-        lo = 1;
-        hi = ax.nbins;
+    int32_t s[U];
+    float z[U];
+    seg_and_z_batch<U>(x, ax, s, z);
+    ModelSeg m[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        m[j] = model[s[j]];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const float y = model_eval(m[j], z[j]);
+        // clamp before converting so ai + offset stays in int32 (an infinite
+        // width becomes the whole axis)
+        const float ylo = __builtin_fminf(__builtin_fmaxf(__builtin_ceilf(y), -0x1p30f), 0x1p30f);
+        const float yhi =
+            __builtin_fminf(__builtin_fmaxf(__builtin_floorf(y + half_hi(m[j].cw)), -0x1p30f), 0x1p30f);
+        const int32_t l = m[j].ai + (int32_t)ylo;
+        const int32_t h = m[j].ai + (int32_t)yhi;
+        int32_t a = l < 1 ? 1 : (l > ax.nbins ? ax.nbins : l);
+        int32_t b = h < 1 ? 1 : (h > ax.nbins ? ax.nbins : h);
+        const bool bad = a > b;
+        a = bad ? 1 : a;
+        b = bad ? ax.nbins : b;
+        const bool under = x[j] < ax.xmin;
+        const bool inside = x[j] < ax.xmax;   // false for NaN
+        const int32_t flow = under ? 0 : ax.nbins + 1;
+        lo[j] = (under || !inside) ? flow : a;
+        hi[j] = (under || !inside) ? flow : b;
     }
 }
 
@@ -237,28 +292,32 @@ __device__ __forceinline__ void search_lockstep(const double (&x)[U], const doub
     }
 }
 
-// Bins of U coordinates on one axis.  KIND is the axis kind when known at
-// compile time, or -1 to dispatch on ax.kind (uniform across a wave).
-// `smem` is the kernel's dynamic LDS array, holding the staged learned models.
+// Bins of U coordinates on one axis, in two halves so that a caller can issue
+// other memory loads in between: axis_bins_begin bounds every bin to [lo, hi]
+// (a single value for fixed-width axes and under/overflow) and issues the edge
+// loads of the first halving step; axis_bins_finish completes the searches.
+// Global loads complete in issue order, so loads issued between the two halves
+// (the next batch of events) are not waited for by the first step.  KIND is
+// the axis kind when known at compile time, or -1 to dispatch on ax.kind
+// (uniform across a wave).  `smem` is the kernel's dynamic LDS array, holding
+// the staged learned models.
 template <int U, int KIND = -1>
-__device__ __forceinline__ void axis_bins(const double (&x)[U], const AxisDev &ax,
-                                          const char *smem, int32_t (&b)[U])
+__device__ __forceinline__ void axis_bins_begin(const double (&x)[U], const AxisDev &ax,
+                                                const char *smem, int32_t (&lo)[U],
+                                                int32_t (&hi)[U], double (&ev)[U])
 {
     const int kind = KIND >= 0 ? KIND : ax.kind;
     if (kind == AX_UNIFORM) {
+        bins_uniform<U>(x, ax, lo);
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            b[j] = bin_uniform(x[j], ax);
+            hi[j] = lo[j];
         return;
     }
-    int32_t lo[U], hi[U];
     if (kind == AX_LEARNED) {
         // kernels always stage the model in LDS; deriving the pointer from the
         // LDS array keeps these reads ds_read instructions (not flat loads)
-        const ModelSeg *m = reinterpret_cast<const ModelSeg *>(smem + ax.lds_model);
-#pragma unroll
-        for (int j = 0; j < U; ++j)
-            learned_interval(x[j], ax, m, lo[j], hi[j]);
+        learned_intervals<U>(x, ax, reinterpret_cast<const ModelSeg *>(smem + ax.lds_model), lo, hi);
     } else {
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -272,10 +331,60 @@ __device__ __forceinline__ void axis_bins(const double (&x)[U], const AxisDev &a
             }
         }
     }
-    search_lockstep<U>(x, ax.edges, lo, hi);
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        if (lo[j] < hi[j])
+            ev[j] = ax.edges[((lo[j] + hi[j] + 1) >> 1) - 1];
+}
+
+template <int U, int KIND = -1>
+__device__ __forceinline__ void axis_bins_finish(const double (&x)[U], const AxisDev &ax,
+                                                 int32_t (&lo)[U], int32_t (&hi)[U],
+                                                 const double (&ev)[U], int32_t (&b)[U])
+{
+    const int kind = KIND >= 0 ? KIND : ax.kind;
+    if (kind != AX_UNIFORM) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (lo[j] < hi[j]) {
+                const int32_t m = (lo[j] + hi[j] + 1) >> 1;
+                if (!(x[j] < ev[j]))
+                    lo[j] = m;
+                else
+                    hi[j] = m - 1;
+            }
+        }
+        search_lockstep<U>(x, ax.edges, lo, hi);
+    }
 #pragma unroll
     for (int j = 0; j < U; ++j)
         b[j] = lo[j];
+}
+
+template <int U, int KIND = -1>
+__device__ __forceinline__ void axis_bins(const double (&x)[U], const AxisDev &ax,
+                                          const char *smem, int32_t (&b)[U])
+{
+    int32_t lo[U], hi[U];
+    double ev[U];
+    axis_bins_begin<U, KIND>(x, ax, smem, lo, hi, ev);
+    axis_bins_finish<U, KIND>(x, ax, lo, hi, ev, b);
+}
+
+// Copies the learned models of the first D axes to their LDS offsets.
+template <int D>
+__device__ __forceinline__ void stage_models(const AxisDev (&ax)[kMaxDims], char *smem)
+{
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (ax[a].kind == AX_LEARNED && ax[a].lds_model >= 0) {
+            const double *src = reinterpret_cast<const double *>(ax[a].model);
+            double *dst = reinterpret_cast<double *>(smem + ax[a].lds_model);
+            const int nd = ax[a].nseg * (int)(sizeof(ModelSeg) / sizeof(double));
+            for (int i = threadIdx.x; i < nd; i += blockDim.x)
+                dst[i] = src[i];
+        }
+    }
 }
 
 // Kernel specializations by the kinds of the axes.

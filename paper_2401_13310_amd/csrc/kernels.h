@@ -83,6 +83,24 @@ struct TileArgs {
     double *sumw, *sumw2;
 };
 
+// The partitioned strategy: events are counted per bucket (a range of
+// 2^bshift consecutive global bins) per workgroup, the counts are scanned into
+// slots, and the events are written in bucket order as in-bucket offsets.
+struct PartArgs {
+    uint32_t *table;          // [nbuckets * G] counts per (bucket, workgroup), then first slots
+    uint32_t *bucket_start;   // [nbuckets + 1] first slot of every bucket, then the total
+    uint16_t *rec_off;        // [m] bin offset within the bucket, in bucket order
+    double *rec_w;            // [m] weights in bucket order (weighted fills)
+    int64_t T;                // total bins
+    int32_t nbuckets;
+    int32_t bshift;           // log2 of the bucket width, <= 16
+    int32_t lds_buckets;      // byte offset of the per-bucket counters in LDS
+    int32_t pad;
+};
+
+// Raises a kernel's dynamic LDS limit to the whole 160 KB (once per kernel).
+void allow_big_lds_ptr(const void *kernel);
+
 // Launchers (return the launch status).
 hipError_t launch_fill(int dims, bool f32, int acc, bool weighted, int threads, int blocks,
                        size_t lds, const FillArgs &a, hipStream_t s);
@@ -93,6 +111,13 @@ hipError_t launch_tiled_bins(int dims, bool f32, bool weighted, int threads, int
                              size_t lds, const FillArgs &a, hipStream_t s);
 hipError_t launch_tile(int acc, bool f32, int threads, int blocks_x, int tiles, size_t lds,
                        const TileArgs &t, hipStream_t s);
+hipError_t launch_part_count(int dims, bool f32, bool weighted, int threads, int blocks, size_t lds,
+                             const FillArgs &a, const PartArgs &p, hipStream_t s);
+hipError_t launch_part_scan(const PartArgs &p, int blocks, hipStream_t s);
+hipError_t launch_part_scatter(bool f32, bool weighted, int threads, int blocks, size_t lds,
+                               const FillArgs &a, const PartArgs &p, hipStream_t s);
+hipError_t launch_part_accum(bool weighted, int threads, size_t lds, const FillArgs &a,
+                             const PartArgs &p, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_add_u64_to_f64(double *dst, const uint64_t *src, int64_t n, hipStream_t s);

@@ -29,6 +29,7 @@ struct Plan {
     int lds = 0;                     // dynamic LDS bytes per workgroup
     int lds_cache = -1;              // out-of-window hot-bin cache offset, -1: none
     int cache_slots = 0;
+    int bucket_bits = 0;             // PART: log2 of the bucket width in bins
 };
 
 // Choices the autotuner (or a test) fixes for a shape; 0 / -1 mean "heuristic".
@@ -40,6 +41,7 @@ struct PlanChoice {
     int merge = -1;
     int64_t win_lo = -1;
     int threads = 0;         // threads per workgroup (0: heuristic)
+    int bucket_bits = 0;     // PART: log2 bucket width (0: heuristic)
 };
 
 }  // namespace hg
@@ -67,6 +69,8 @@ struct hist_s {
     size_t stage_bytes = 0;
     int32_t *d_gbins = nullptr;
     int64_t gbins_cap = 0;
+    void *d_part = nullptr;                              // PART scratch
+    size_t part_bytes = 0;
     int64_t entries = 0;
     hg::PlanChoice forced;                               // hist_set_strategy
     // kernel timing (hist_timing): event pairs around the fill and merge kernels
@@ -97,6 +101,9 @@ hist_status run_plan(hist_s *h, const Plan &p, const void *const *coords, const 
 size_t stage_bytes_for(const Plan &p);
 int64_t stage_stride_for(const Plan &p);
 int64_t tiled_chunk(const hist_s *h);
+int64_t part_chunk(const hist_s *h);
+// Smallest and largest log2 bucket width a PART plan can use (lo > hi: none).
+void part_bits_range(const hist_s *h, bool weighted, int lds_base, int &lo, int &hi);
 int unroll_of(int dims, bool f32, bool weighted);
 
 }  // namespace hg

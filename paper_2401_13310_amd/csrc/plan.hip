@@ -56,6 +56,28 @@ int64_t tiled_chunk(const hist_s *h)
     return (int64_t)1 << 24;
 }
 
+int64_t part_chunk(const hist_s *h)
+{
+    (void)h;
+    return (int64_t)1 << 25;
+}
+
+// Bucket widths 2^b a PART plan can use: the bucket's bins must fit LDS in the
+// accumulate pass (4 or 16 bytes a bin), its offsets 16 bits (b <= 16), and the
+// per-bucket counters of the count and scatter passes must fit LDS after the
+// statistics and models.
+void part_bits_range(const hist_s *h, bool weighted, int lds_base, int &lo, int &hi)
+{
+    const int per_bin = weighted ? 16 : 4;
+    hi = 0;
+    while (hi < 16 && ((int64_t)per_bin << (hi + 1)) <= h->lds_max)
+        ++hi;
+    const int64_t max_buckets = (h->lds_max - lds_base) / 4;
+    lo = 6;
+    while (lo <= hi && ((h->T + ((int64_t)1 << lo) - 1) >> lo) > max_buckets)
+        ++lo;
+}
+
 static int window_bytes(int acc, int64_t len, int copies)
 {
     if (acc == ACC_U16)
@@ -84,6 +106,8 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
         acc = (h->T * 4 <= avail) ? ACC_U32 : ACC_U16;
     const int64_t cap = acc == ACC_U16 ? (int64_t)(avail / 4) * 2 : avail / acc_bytes(acc);
 
+    int plo = 0, phi = -1;
+    part_bits_range(h, weighted, base, plo, phi);
     int strategy = c.strategy;
     if (strategy == HIST_STRAT_AUTO) {
         if (h->T <= cap) {
@@ -92,10 +116,27 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
             strategy = HIST_STRAT_LDS;   // a window over most bins, the rest global
         } else {
             const int64_t tiles = (h->T + cap - 1) / cap;
-            strategy = tiles <= 16 ? HIST_STRAT_TILED : HIST_STRAT_GLOBAL;
+            strategy = tiles <= 2 ? HIST_STRAT_TILED
+                                  : (plo <= phi ? HIST_STRAT_PART : HIST_STRAT_GLOBAL);
         }
     }
+    if (strategy == HIST_STRAT_PART && plo > phi)
+        strategy = HIST_STRAT_GLOBAL;   // too many bins to partition by LDS-sized ranges
     p.strategy = strategy;
+
+    if (strategy == HIST_STRAT_PART) {
+        p.acc = weighted ? ACC_F64 : ACC_U32;
+        int b = c.bucket_bits > 0 ? c.bucket_bits : (weighted ? 12 : 13);
+        b = std::min(std::max(b, plo), phi);
+        p.bucket_bits = b;
+        p.win_len = 1 << b;
+        p.copies = 1;
+        p.merge = MERGE_ATOMIC;
+        const int64_t nb = (h->T + p.win_len - 1) >> b;
+        p.lds = base + (int)(nb * 4);
+        p.blocks = c.blocks > 0 ? c.blocks : h->num_cu * 2;
+        return p;
+    }
 
     if (strategy == HIST_STRAT_GLOBAL) {
         p.acc = weighted ? ACC_F64 : ACC_U32;
@@ -231,7 +272,7 @@ extern "C" hist_status hist_set_strategy(hist_t *h, int strategy, int blocks, in
 {
     if (!h)
         return set_error(HIST_EINVAL, "hist_set_strategy: NULL handle");
-    if (strategy < HIST_STRAT_AUTO || strategy > HIST_STRAT_TILED)
+    if (strategy < HIST_STRAT_AUTO || strategy > HIST_STRAT_PART)
         return set_error(HIST_EINVAL, "hist_set_strategy: unknown strategy %d", strategy);
     if (blocks < 0 || subhists < 0 || subhists > 64)
         return set_error(HIST_EINVAL, "hist_set_strategy: blocks >= 0, 0 <= subhists <= 64");
@@ -242,6 +283,7 @@ extern "C" hist_status hist_set_strategy(hist_t *h, int strategy, int blocks, in
     c.merge = h->forced.merge;
     c.win_lo = h->forced.win_lo;
     c.threads = h->forced.threads;
+    c.bucket_bits = h->forced.bucket_bits;
     h->forced = c;
     return HIST_OK;
 }
@@ -399,9 +441,21 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
 
     // candidates
     std::vector<PlanChoice> cands;
-    for (int strat : {HIST_STRAT_LDS, HIST_STRAT_GLOBAL, HIST_STRAT_TILED}) {
-        if (strat == HIST_STRAT_TILED && p0.acc != ACC_U16 && h->T * 16 <= h->lds_max)
+    for (int strat : {HIST_STRAT_LDS, HIST_STRAT_GLOBAL, HIST_STRAT_TILED, HIST_STRAT_PART}) {
+        if ((strat == HIST_STRAT_TILED || strat == HIST_STRAT_PART) && p0.acc != ACC_U16 &&
+            h->T * 16 <= h->lds_max)
             continue;
+        if (strat == HIST_STRAT_PART) {
+            int lo = 0, hi = -1;
+            part_bits_range(h, weighted, p0.lds_base, lo, hi);
+            for (int b = std::max(lo, 11); b <= hi; ++b) {
+                PlanChoice c;
+                c.strategy = strat;
+                c.bucket_bits = b;
+                cands.push_back(c);
+            }
+            continue;
+        }
         if (strat == HIST_STRAT_LDS) {
             for (int thr : {512, 1024}) {
                 for (int bpc : {1, 2}) {
@@ -466,8 +520,9 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
         g_cache[shape_key(h, weighted, f32)] = best;
     }
     if (std::getenv("HIST_LOG"))
-        fprintf(stderr, "hist_tune: T=%lld n=%lld -> strategy %d bpc %d merge %d win_lo %lld (%.3f ms)\n",
+        fprintf(stderr, "hist_tune: T=%lld n=%lld -> strategy %d bpc %d merge %d win_lo %lld "
+                        "bucket_bits %d (%.3f ms)\n",
                 (long long)h->T, (long long)n, best.strategy, best.blocks_per_cu, best.merge,
-                (long long)best.win_lo, best_ms);
+                (long long)best.win_lo, best.bucket_bits, best_ms);
     return st;
 }

@@ -133,6 +133,40 @@ def test_batch_mixed_dtypes_unit_weights_and_empty(hg):
         check_member(h, m)
 
 
+def test_batch_partitioned_members(hg):
+    """Members far larger than LDS with many events go through the count /
+    scan / scatter / accumulate passes; replays add up."""
+    import torch
+    rng = np.random.default_rng(123)
+    e = np.sort(rng.uniform(0.0, 10.0, 100_001))
+    members = [
+        {"axes": [{"nbins": 300_000, "xmin": -4.0, "xmax": 4.0}],
+         "coords": [rng.normal(0, 1, 400_003)], "weights": rng.uniform(0, 2, 400_003)},
+        {"axes": [{"nbins": 100_000, "edges": e}],
+         "coords": [rng.exponential(2.0, 300_001)], "weights": None},
+        {"axes": [{"nbins": 100, "xmin": -4.0, "xmax": 4.0}] * 3,
+         "coords": [rng.normal(0, 1, 200_000) for _ in range(3)], "weights": None},
+        {"axes": [{"nbins": 1000, "xmin": 0.0, "xmax": 1.0}, {"nbins": 500, "xmin": 0.0, "xmax": 1.0}],
+         "coords": [rng.uniform(-0.1, 1.1, 70_000), rng.uniform(-0.1, 1.1, 70_000)],
+         "weights": rng.uniform(0, 2, 70_000)},
+        {"axes": [{"nbins": 50, "xmin": -3.0, "xmax": 3.0}],
+         "coords": [rng.normal(0, 1, 100_000)], "weights": None},
+    ]
+    dtypes = [None, None, torch.float32, torch.float32, None]
+    hists, cols, ws = build(hg, members, learned=True, dtypes=dtypes)
+    b = hg.Batch(hists, cols, ws)
+    b.launch(graph=True)
+    b.launch(graph=True)
+    torch.cuda.synchronize()
+    for i, (h, m) in enumerate(zip(hists, members)):
+        if dtypes[i] is torch.float32:
+            m = dict(m)
+            m["coords"] = [c.astype(np.float32).astype(np.float64) for c in m["coords"]]
+            if m["weights"] is not None:
+                m["weights"] = m["weights"].astype(np.float32).astype(np.float64)
+        check_member(h, m, times=2)
+
+
 def test_batch_rejects_bad_arguments(hg):
     h = hg.Hist([{"nbins": 10, "xmin": 0.0, "xmax": 1.0}])
     x = dev(np.zeros(10))

@@ -184,15 +184,15 @@ def test_fill_variable_1d_window_merges(hg, merge):
                      learned=True, window=(20_000, merge))
 
 
-@pytest.mark.parametrize("strategy", ["lds", "global", "tiled"])
+@pytest.mark.parametrize("strategy", ["lds", "global", "tiled", "part"])
 def test_fill_corr_3d(hg, strategy):
     wl = synth.corr_3d(2_000_000)
     s = {"lds": hg.HIST_STRAT_LDS, "global": hg.HIST_STRAT_GLOBAL,
-         "tiled": hg.HIST_STRAT_TILED}[strategy]
+         "tiled": hg.HIST_STRAT_TILED, "part": hg.HIST_STRAT_PART}[strategy]
     fill_and_compare(hg, wl["axes"], wl["coords"], None, strategy=s)
 
 
-@pytest.mark.parametrize("strategy", ["auto", "lds", "global", "tiled"])
+@pytest.mark.parametrize("strategy", ["auto", "lds", "global", "tiled", "part"])
 def test_fill_weighted_2d_mixed_axes(hg, strategy):
     rng = np.random.default_rng(21)
     e = np.sort(rng.uniform(-3, 3, 301))
@@ -201,8 +201,44 @@ def test_fill_weighted_2d_mixed_axes(hg, strategy):
     coords = [rng.normal(0, 1, n), rng.normal(0, 1, n)]
     w = rng.uniform(0.0, 2.0, n)
     s = {"auto": None, "lds": hg.HIST_STRAT_LDS, "global": hg.HIST_STRAT_GLOBAL,
-         "tiled": hg.HIST_STRAT_TILED}[strategy]
+         "tiled": hg.HIST_STRAT_TILED, "part": hg.HIST_STRAT_PART}[strategy]
     fill_and_compare(hg, axes, coords, w, strategy=s, learned=True)
+
+
+# The partitioned strategy: a learned variable axis of 1e5 bins (ragged last
+# bucket), FP32 weighted input, a 3D histogram whose event count spans two
+# partition chunks (2^25 events each), and few events over many buckets.
+def test_fill_part_variable_learned(hg):
+    wl = synth.variable_1d(3_000_017)
+    fill_and_compare(hg, wl["axes"], wl["coords"], None, strategy=hg.HIST_STRAT_PART,
+                     learned=True)
+
+
+def test_fill_part_weighted_f32(hg):
+    import torch
+    rng = np.random.default_rng(41)
+    axes = [{"nbins": 250_000, "xmin": -4.0, "xmax": 4.0}]
+    n = 2_000_001
+    x = rng.normal(0, 1.3, n)
+    w = rng.lognormal(0.0, 1.0, n)
+    fill_and_compare(hg, axes, [x], w, strategy=hg.HIST_STRAT_PART, dtype=torch.float32)
+
+
+def test_fill_part_two_chunks(hg):
+    rng = np.random.default_rng(42)
+    axes = [{"nbins": 60, "xmin": -3.0, "xmax": 3.0}, {"nbins": 70, "xmin": -3.0, "xmax": 3.0},
+            {"nbins": 80, "xmin": -3.0, "xmax": 3.0}]
+    n = (1 << 25) + 4099
+    coords = [rng.normal(0, 1, n) for _ in range(3)]
+    fill_and_compare(hg, axes, coords, None, strategy=hg.HIST_STRAT_PART)
+
+
+def test_fill_part_sparse(hg):
+    rng = np.random.default_rng(43)
+    axes = [{"nbins": 1_000_000, "xmin": 0.0, "xmax": 1.0}]
+    x = rng.uniform(-0.1, 1.1, 777)
+    w = rng.uniform(0.0, 2.0, 777)
+    fill_and_compare(hg, axes, [x], w, strategy=hg.HIST_STRAT_PART)
 
 
 def test_fill_weighted_signed_weights(hg):
