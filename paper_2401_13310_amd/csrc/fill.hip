@@ -195,23 +195,39 @@ __device__ __forceinline__ void cache_flush(const FillArgs &A, char *smem)
 }
 
 // Coalesced streaming loads of U events per thread: event base + j*blockDim +
-// tid of the block's range, addressed as 32-bit offsets from the block's
-// (wave-uniform) column pointers.  Offsets past the block's length (len >= 1)
-// load the last event instead; process_batch skips them.  Every load is issued
-// unconditionally, so the waits for loads issued before these stay exact.
-// Non-temporal, so the event stream does not evict edges and models.
+// tid of the block's range, through buffer descriptors over the block's
+// columns.  A descriptor covers exactly the block's len events, so loads past
+// the end return 0 without touching memory (process_batch skips those
+// events); every load is issued unconditionally, so the waits for loads issued
+// before these stay exact.  Non-temporal, so the event stream does not evict
+// edges and models.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t column_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ T buffer_load_nt(__amdgpu_buffer_rsrc_t r, uint32_t off)
+{
+    constexpr int kNonTemporal = 2;
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, kNonTemporal));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, kNonTemporal));
+}
+
 template <int D, typename T, bool W, int U>
-__device__ __forceinline__ void load_batch(const T *const (&xb)[D], const T *wb, uint32_t base,
-                                           uint32_t len, T (&x)[U][D], T (&w)[U])
+__device__ __forceinline__ void load_batch(const __amdgpu_buffer_rsrc_t (&rx)[D],
+                                           __amdgpu_buffer_rsrc_t rw, uint32_t base,
+                                           T (&x)[U][D], T (&w)[U])
 {
 #pragma unroll
     for (int j = 0; j < U; ++j) {
-        const uint32_t i = base + (uint32_t)j * blockDim.x + threadIdx.x;
-        const uint32_t ic = i < len ? i : len - 1;
+        const uint32_t off = (base + (uint32_t)j * blockDim.x + threadIdx.x) * (uint32_t)sizeof(T);
 #pragma unroll
         for (int a = 0; a < D; ++a)
-            x[j][a] = __builtin_nontemporal_load(xb[a] + ic);
-        w[j] = W ? __builtin_nontemporal_load(wb + ic) : T(0);
+            x[j][a] = buffer_load_nt<T>(rx[a], off);
+        w[j] = W ? buffer_load_nt<T>(rw, off) : T(0);
     }
 }
 
@@ -361,18 +377,21 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
     // iteration reloads the block's last event, unused).
     const uint32_t len = (uint32_t)(end > start ? end - start : 0);
     const uint32_t step = (uint32_t)nthr * U;
-    const T *xb[D];
+    // the plan keeps a block's range under 2^32 bytes
+    const uint32_t bytes = len * (uint32_t)sizeof(T);
+    __amdgpu_buffer_rsrc_t xb[D];
 #pragma unroll
     for (int a = 0; a < D; ++a)
-        xb[a] = static_cast<const T *>(A.coords[a]) + start;
-    const T *wb = W ? static_cast<const T *>(A.w) + start : nullptr;
+        xb[a] = column_rsrc(static_cast<const T *>(A.coords[a]) + start, bytes);
+    const __amdgpu_buffer_rsrc_t wb =
+        column_rsrc(W ? static_cast<const T *>(A.w) + start : static_cast<const T *>(A.coords[0]), W ? bytes : 0u);
     T cx[U][D], cw[U];
     if (len > 0)
-        load_batch<D, T, W, U>(xb, wb, 0, len, cx, cw);
+        load_batch<D, T, W, U>(xb, wb, 0, cx, cw);
     for (uint32_t base = 0; base < len; base += step) {
         T nx[U][D], nw[U];
         process_batch<D, T, ACC, W, U, KS>(A, smem, win, cx, cw, base, len, cp, st, nin, [&] {
-            load_batch<D, T, W, U>(xb, wb, base + step, len, nx, nw);
+            load_batch<D, T, W, U>(xb, wb, base + step, nx, nw);
         });
         if (ACC == ACC_U16 && ++it == A.epoch_iters) {
             it = 0;

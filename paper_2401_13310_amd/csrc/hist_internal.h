@@ -135,11 +135,14 @@ __device__ __forceinline__ uint32_t key_feature(double x, const AxisDev &ax)
     return k - ax.key0;
 }
 
+// The segments cover the keys of [e[0], e[nbins]], so for in-range x the
+// clamp of s never acts and z is the key's offset in its segment; the clamp
+// keeps the model read in bounds for any other x (whose result is discarded).
 __device__ __forceinline__ void key_seg(uint32_t f, const AxisDev &ax, int32_t &s, float &z)
 {
     const uint32_t sf = f >> ax.kshift;
     s = (int32_t)(sf < (uint32_t)(ax.nseg - 1) ? sf : (uint32_t)(ax.nseg - 1));
-    z = (float)(f - ((uint32_t)s << ax.kshift)) * ax.zscale;
+    z = (float)(f & ax.kmask) * ax.zscale;
 }
 
 __device__ __forceinline__ void linear_seg(double x, const AxisDev &ax, int32_t &s, float &z)
@@ -168,10 +171,12 @@ __device__ __forceinline__ void seg_and_z_batch(const double (&x)[U], const Axis
 {
     if (ax.feature == FEAT_KEY) {
         if (ax.keypos) {
+            // in-range x is positive, so setting the sign bit of its high
+            // word is adding 2^31 (other x get a discarded result)
+            const uint32_t kadd = 0x80000000u - ax.key0;
 #pragma unroll
             for (int j = 0; j < U; ++j)
-                key_seg(((uint32_t)((uint64_t)__double_as_longlong(x[j]) >> 32) | 0x80000000u) - ax.key0,
-                        ax, s[j], z[j]);
+                key_seg((uint32_t)((uint64_t)__double_as_longlong(x[j]) >> 32) + kadd, ax, s[j], z[j]);
         } else {
 #pragma unroll
             for (int j = 0; j < U; ++j)
@@ -229,8 +234,8 @@ __device__ __forceinline__ void learned_intervals(const double (&x)[U], const Ax
             __builtin_fminf(__builtin_fmaxf(__builtin_floorf(y + half_hi(m[j].cw)), -0x1p30f), 0x1p30f);
         const int32_t l = m[j].ai + (int32_t)ylo;
         const int32_t h = m[j].ai + (int32_t)yhi;
-        int32_t a = l < 1 ? 1 : (l > ax.nbins ? ax.nbins : l);
-        int32_t b = h < 1 ? 1 : (h > ax.nbins ? ax.nbins : h);
+        int32_t a = __builtin_elementwise_min(__builtin_elementwise_max(l, 1), ax.nbins);
+        int32_t b = __builtin_elementwise_min(__builtin_elementwise_max(h, 1), ax.nbins);
         const bool bad = a > b;
         a = bad ? 1 : a;
         b = bad ? ax.nbins : b;
@@ -332,9 +337,11 @@ __device__ __forceinline__ void axis_bins_begin(const double (&x)[U], const Axis
         }
     }
 #pragma unroll
-    for (int j = 0; j < U; ++j)
+    for (int j = 0; j < U; ++j) {
+        ev[j] = 0.0;
         if (lo[j] < hi[j])
             ev[j] = ax.edges[((lo[j] + hi[j] + 1) >> 1) - 1];
+    }
 }
 
 template <int U, int KIND = -1>
@@ -344,17 +351,19 @@ __device__ __forceinline__ void axis_bins_finish(const double (&x)[U], const Axi
 {
     const int kind = KIND >= 0 ? KIND : ax.kind;
     if (kind != AX_UNIFORM) {
+        bool open = false;
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            if (lo[j] < hi[j]) {
-                const int32_t m = (lo[j] + hi[j] + 1) >> 1;
-                if (!(x[j] < ev[j]))
-                    lo[j] = m;
-                else
-                    hi[j] = m - 1;
-            }
+            const bool step = lo[j] < hi[j];
+            const int32_t m = (lo[j] + hi[j] + 1) >> 1;
+            const bool ge = !(x[j] < ev[j]);
+            lo[j] = (step && ge) ? m : lo[j];
+            hi[j] = (step && !ge) ? m - 1 : hi[j];
+            open = open || lo[j] < hi[j];
         }
-        search_lockstep<U>(x, ax.edges, lo, hi);
+        // after the learned index one step usually decides every bin
+        if (__builtin_amdgcn_ballot_w64(open))
+            search_lockstep<U>(x, ax.edges, lo, hi);
     }
 #pragma unroll
     for (int j = 0; j < U; ++j)

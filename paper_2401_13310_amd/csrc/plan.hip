@@ -200,6 +200,10 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
     const int64_t need = (n + step - 1) / step;
     if (G > need)
         G = need;
+    // a block addresses its events with 32-bit byte offsets
+    constexpr int64_t kMaxBlockEvents = (int64_t)1 << 28;
+    if (G < (n + kMaxBlockEvents - 1) / kMaxBlockEvents)
+        G = (n + kMaxBlockEvents - 1) / kMaxBlockEvents;
     if (G < 1)
         G = 1;
     int64_t per = (n + G - 1) / G;
