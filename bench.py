@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--no-bsearch", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM traffic per launch measured with rocprofv3 counters")
-    ap.add_argument("--ingest", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+    ap.add_argument("--ingest", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PLAN_JSON"),
                     help="read two rocprofv3 --pmc databases of a --profile run (FETCH_SIZE, "
                          "then WRITE_SIZE), scale each by the copy kernel of known size, and "
                          "record the fill kernel's HBM bytes per launch in --traffic")
@@ -53,16 +53,18 @@ def parse():
     return ap.parse_args()
 
 
+FILL_SOURCES = ("fill.hip", "hist_internal.h", "device_common.h", "kernels.h")
+
+
 def kernel_source_hash():
-    """Hash of the HIP sources: counter-derived traffic is valid only for the
-    kernels it was measured on."""
+    """Hash of the sources the fill kernels compile from: counter-derived
+    traffic is valid only for the kernels it was measured on."""
     import hashlib
     d = os.path.join(ROOT, "paper_2401_13310_amd", "csrc")
     hs = hashlib.sha256()
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h")):
-            with open(os.path.join(d, name), "rb") as f:
-                hs.update(name.encode() + b"\0" + f.read())
+    for name in FILL_SOURCES:
+        with open(os.path.join(d, name), "rb") as f:
+            hs.update(name.encode() + b"\0" + f.read())
     return hs.hexdigest()[:16]
 
 
@@ -142,16 +144,17 @@ def cpu_baseline(wl, n):
                       % (n, dt)}
 
 
-def load_traffic(path, workload, n):
+def load_traffic(path, workload, n, plan):
     """HBM bytes per fill launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy
-    of known size), if measured on the current kernel sources."""
+    of known size), if measured on the current kernel sources and plan."""
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     rec = t.get(workload)
-    if not rec or rec.get("events") != n or rec.get("source_hash") != kernel_source_hash():
+    if (not rec or rec.get("events") != n or rec.get("source_hash") != kernel_source_hash()
+            or rec.get("plan") != plan):
         return None
     return rec.get("bytes_per_launch")
 
@@ -185,24 +188,29 @@ def _counter_per_dispatch(path, counter):
 def ingest(args):
     fetch = _counter_per_dispatch(args.ingest[0], "FETCH_SIZE")
     write = _counter_per_dispatch(args.ingest[1], "WRITE_SIZE")
-    copy = [k for k in fetch if "copy" in k.lower() and "hg::" not in k]
-    copy += [k for k in fetch if "elementwise" in k.lower() and "hg::" not in k]
+    # calibration: the elementwise copy the profile run makes last (reads and
+    # writes one column); the runtime's own copy kernels also move host data
+    copy = [k for k in fetch if "elementwise" in k.lower() and "hg::" not in k and k in write]
     fill = [k for k in fetch if "fill_kernel" in k]
     if not copy or not fill:
         raise SystemExit("ingest: need the fill kernel and the calibration copy in both runs")
     wl = build_workload(args.workload, args.events)
     n = wl["coords"][0].size
     known = n * wl["coords"][0].dtype.itemsize            # bytes read and written by each copy
-    ck = copy[0]
-    f_copy = sorted(fetch[ck])[len(fetch[ck]) // 2] * 1024.0
-    w_copy = sorted(write[ck])[len(write[ck]) // 2] * 1024.0
+    ck = copy[-1]
+    f_copy = sorted(fetch[ck][-3:])[len(fetch[ck][-3:]) // 2] * 1024.0
+    w_copy = sorted(write[ck][-3:])[len(write[ck][-3:]) // 2] * 1024.0
     fk = max(fill, key=lambda k: len(fetch[k]))
     last = max(1, args.steps)                 # the fills after tuning are the last ones
     fv, wv = sorted(fetch[fk][-last:]), sorted(write[fk][-last:])
     f_fill = fv[len(fv) // 2] * 1024.0
     w_fill = wv[len(wv) // 2] * 1024.0
     sf, sw = known / f_copy, known / w_copy
-    rec = {"events": n, "kernel": fk, "source_hash": kernel_source_hash(),
+    with open(args.ingest[2]) as f:
+        prof = json.load(f)
+    if prof.get("source_hash") != kernel_source_hash() or prof.get("events") != n:
+        raise SystemExit("ingest: the profile run used other kernel sources or sizes")
+    rec = {"events": n, "kernel": fk, "source_hash": kernel_source_hash(), "plan": prof["plan"],
            "fetch_kib_raw": f_fill / 1024.0, "write_kib_raw": w_fill / 1024.0,
            "copy_kernel": ck, "copy_bytes": known, "fetch_scale": sf, "write_scale": sw,
            "bytes_per_launch": f_fill * sf + w_fill * sw}
@@ -345,6 +353,10 @@ def main():
         print("profile run: %d fills of %d events, plan %s; copy of %d bytes x3; sources %s"
               % (args.steps, n, plan, cols[0].numel() * cols[0].element_size(),
                  kernel_source_hash()), flush=True)
+        os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
+        with open(os.path.join(ROOT, "gpurun_out", "profile_plan_%s.json" % args.workload), "w") as f:
+            json.dump({"workload": args.workload, "events": n, "plan": plan,
+                       "source_hash": kernel_source_hash()}, f)
         h.close()
         return
 
@@ -357,7 +369,7 @@ def main():
     merge_ms = kt["merge_ms"] / max(1, kt["launches"])
     B, per_event = alg_bytes(wl, n)
     achieved = B / (fill_ms * 1e-3) / 1e9
-    traffic = load_traffic(args.traffic, args.workload, n)
+    traffic = load_traffic(args.traffic, args.workload, n, plan)
 
     out = {
         "metric": METRIC,

@@ -490,30 +490,44 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    float best_ms = 1e30f;
-    PlanChoice best = cands.empty() ? auto_c : cands[0];
-    for (const PlanChoice &c : cands) {
+    // the heuristic plan goes first; another candidate replaces it only when
+    // it is clearly faster, so that near-ties do not flip between runs
+    PlanChoice heur = auto_c;
+    heur.strategy = p0.strategy;
+    heur.win_lo = win_lo;
+    cands.insert(cands.begin(), heur);
+    float best_ms = 1e30f, heur_ms = 1e30f;
+    PlanChoice best = heur;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        const PlanChoice &c = cands[ci];
         Plan p = plan_from_choice(h, n, dtype, weighted, c);
         if (p.strategy != c.strategy)
             continue;
         st = run_plan(h, p, coords, weights, n, dtype, s);   // warm-up (and allocations)
         if (st != HIST_OK)
             continue;
-        std::vector<float> ts;
-        for (int r = 0; r < 3; ++r) {
+        float tmin = 1e30f;
+        for (int r = 0; r < 5; ++r) {
             (void)hipEventRecord(e0, s);
             st = run_plan(h, p, coords, weights, n, dtype, s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e0, e1);
-            ts.push_back(ms);
+            tmin = std::min(tmin, ms);
         }
-        std::sort(ts.begin(), ts.end());
-        if (st == HIST_OK && ts[1] < best_ms) {
-            best_ms = ts[1];
+        if (st != HIST_OK)
+            continue;
+        if (ci == 0)
+            heur_ms = tmin;
+        if (tmin < best_ms) {
+            best_ms = tmin;
             best = c;
         }
+    }
+    if (heur_ms <= best_ms * 1.05f) {
+        best = heur;
+        best_ms = heur_ms;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
