@@ -254,12 +254,13 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
     double x[D][U];
     int32_t b[D][U], lo[D][U], hi[D][U];
     double ev[D][U];
+    bool inr[D][U];
 #pragma unroll
     for (int a = 0; a < D; ++a) {
 #pragma unroll
         for (int j = 0; j < U; ++j)
             x[a][j] = (double)cx[j][a];
-        axis_bins_begin<U, KIND>(x[a], A.ax[a], smem, lo[a], hi[a], ev[a]);
+        axis_bins_begin<U, KIND>(x[a], A.ax[a], smem, lo[a], hi[a], ev[a], inr[a]);
     }
     if (!early)
         prefetch();
@@ -284,18 +285,23 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             xe[a] = x[a][j];
-            inside = inside && (uint32_t)(b[a][j] - 1) < (uint32_t)A.ax[a].nbins;
+            inside = inside && inr[a][j];
             g += (a == 0) ? b[a][j] : b[a][j] * A.ax[a].stride;
         }
         gv[j] = g;
         const double w = W ? (double)cw[j] : 1.0;
-        if (ok && inside) {
-            if (W) {
-                stats_add<D>(st, xe, w);
-            } else {
-                stats_add_unit<D>(st, xe);
-                ++nin;
-            }
+        // statistics of in-range events: excluded events add exact zeros
+        // (their coordinates and weight are masked, so no inf or NaN enters)
+        const bool take = ok && inside;
+        double xm[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            xm[a] = take ? xe[a] : 0.0;
+        if (W) {
+            stats_add<D>(st, xm, take ? w : 0.0);
+        } else {
+            stats_add_unit<D>(st, xm);
+            nin += take ? 1u : 0u;
         }
         const uint32_t l = (uint32_t)(g - A.win_lo);
         out[j] = ok && !(l < wlen);

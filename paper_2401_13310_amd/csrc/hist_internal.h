@@ -70,7 +70,7 @@ struct AxisDev {
 // --------------------------------------------------------------------------
 template <int U>
 __device__ __forceinline__ void bins_uniform(const double (&x)[U], const AxisDev &ax,
-                                             int32_t (&b)[U])
+                                             int32_t (&b)[U], bool (&inr)[U])
 {
 #pragma clang fp contract(off)
     double t[U];
@@ -79,6 +79,7 @@ __device__ __forceinline__ void bins_uniform(const double (&x)[U], const AxisDev
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         const bool in = !(x[j] < ax.xmin) && x[j] < ax.xmax;
+        inr[j] = in;
         t[j] = x[j] - ax.xmin;
         const double q = t[j] * ax.guess;
         const double k = __builtin_floor(q);
@@ -215,11 +216,13 @@ __device__ __forceinline__ float model_eval(const ModelSeg &m, float z)
 template <int U>
 __device__ __forceinline__ void learned_intervals(const double (&x)[U], const AxisDev &ax,
                                                   const ModelSeg *__restrict__ model,
-                                                  int32_t (&lo)[U], int32_t (&hi)[U])
+                                                  int32_t (&lo)[U], int32_t (&hi)[U],
+                                                  bool (&inr)[U])
 {
     int32_t s[U];
     float z[U];
     seg_and_z_batch<U>(x, ax, s, z);
+    bool bad = false;
     ModelSeg m[U];
 #pragma unroll
     for (int j = 0; j < U; ++j)
@@ -234,16 +237,24 @@ __device__ __forceinline__ void learned_intervals(const double (&x)[U], const Ax
             __builtin_fminf(__builtin_fmaxf(__builtin_floorf(y + half_hi(m[j].cw)), -0x1p30f), 0x1p30f);
         const int32_t l = m[j].ai + (int32_t)ylo;
         const int32_t h = m[j].ai + (int32_t)yhi;
-        int32_t a = __builtin_elementwise_min(__builtin_elementwise_max(l, 1), ax.nbins);
-        int32_t b = __builtin_elementwise_min(__builtin_elementwise_max(h, 1), ax.nbins);
-        const bool bad = a > b;
-        a = bad ? 1 : a;
-        b = bad ? ax.nbins : b;
+        const int32_t a = __builtin_elementwise_min(__builtin_elementwise_max(l, 1), ax.nbins);
+        const int32_t b = __builtin_elementwise_min(__builtin_elementwise_max(h, 1), ax.nbins);
         const bool under = x[j] < ax.xmin;
-        const bool inside = x[j] < ax.xmax;   // false for NaN
+        const bool in = !under && x[j] < ax.xmax;   // false for NaN
         const int32_t flow = under ? 0 : ax.nbins + 1;
-        lo[j] = (under || !inside) ? flow : a;
-        hi[j] = (under || !inside) ? flow : b;
+        inr[j] = in;
+        lo[j] = in ? a : flow;
+        hi[j] = in ? b : flow;
+        bad = bad || lo[j] > hi[j];
+    }
+    if (__builtin_amdgcn_ballot_w64(bad)) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (lo[j] > hi[j]) {
+                lo[j] = 1;
+                hi[j] = ax.nbins;
+            }
+        }
     }
 }
 
@@ -309,11 +320,11 @@ __device__ __forceinline__ void search_lockstep(const double (&x)[U], const doub
 template <int U, int KIND = -1>
 __device__ __forceinline__ void axis_bins_begin(const double (&x)[U], const AxisDev &ax,
                                                 const char *smem, int32_t (&lo)[U],
-                                                int32_t (&hi)[U], double (&ev)[U])
+                                                int32_t (&hi)[U], double (&ev)[U], bool (&inr)[U])
 {
     const int kind = KIND >= 0 ? KIND : ax.kind;
     if (kind == AX_UNIFORM) {
-        bins_uniform<U>(x, ax, lo);
+        bins_uniform<U>(x, ax, lo, inr);
 #pragma unroll
         for (int j = 0; j < U; ++j)
             hi[j] = lo[j];
@@ -322,18 +333,16 @@ __device__ __forceinline__ void axis_bins_begin(const double (&x)[U], const Axis
     if (kind == AX_LEARNED) {
         // kernels always stage the model in LDS; deriving the pointer from the
         // LDS array keeps these reads ds_read instructions (not flat loads)
-        learned_intervals<U>(x, ax, reinterpret_cast<const ModelSeg *>(smem + ax.lds_model), lo, hi);
+        learned_intervals<U>(x, ax, reinterpret_cast<const ModelSeg *>(smem + ax.lds_model), lo, hi,
+                             inr);
     } else {
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            if (x[j] < ax.xmin) {
-                lo[j] = hi[j] = 0;
-            } else if (!(x[j] < ax.xmax)) {
-                lo[j] = hi[j] = ax.nbins + 1;
-            } else {
-                lo[j] = 1;
-                hi[j] = ax.nbins;
-            }
+            const bool under = x[j] < ax.xmin;
+            inr[j] = !under && x[j] < ax.xmax;
+            const int32_t flow = under ? 0 : ax.nbins + 1;
+            lo[j] = inr[j] ? 1 : flow;
+            hi[j] = inr[j] ? ax.nbins : flow;
         }
     }
 #pragma unroll
@@ -376,7 +385,8 @@ __device__ __forceinline__ void axis_bins(const double (&x)[U], const AxisDev &a
 {
     int32_t lo[U], hi[U];
     double ev[U];
-    axis_bins_begin<U, KIND>(x, ax, smem, lo, hi, ev);
+    bool inr[U];
+    axis_bins_begin<U, KIND>(x, ax, smem, lo, hi, ev, inr);
     axis_bins_finish<U, KIND>(x, ax, lo, hi, ev, b);
 }
 
