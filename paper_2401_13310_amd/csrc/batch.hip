@@ -41,6 +41,7 @@ struct MemberDev {
     double *rec_w;                // [n] weights in bucket order (weighted members)
     uint32_t *table;              // [nbuckets * ntiles]
     uint32_t *bucket_start;       // [nbuckets + 1]
+    uint32_t *chunk_start;        // [nbuckets + 1]
     int64_t T;
     int32_t nbuckets, bshift, ntiles, pad2;
 };
@@ -53,9 +54,9 @@ struct TileDev {
     int32_t pad;
 };
 
-struct BucketDev {
+struct ChunkDev {
     int32_t member;
-    int32_t bucket;
+    int32_t chunk;                // accumulate chunk of the member (may be past its last)
 };
 
 // Events [start, start+len) of member M: find bin, statistics, accumulation.
@@ -252,7 +253,7 @@ __global__ void __launch_bounds__(1024)
 batch_part_scan_kernel(const MemberDev *__restrict__ members, const int32_t *__restrict__ part_members)
 {
     const MemberDev &M = members[part_members[blockIdx.x]];
-    part_scan(M.table, M.bucket_start, M.nbuckets, M.ntiles);
+    part_scan(M.table, M.bucket_start, M.chunk_start, M.nbuckets, M.ntiles);
 }
 
 __global__ void __launch_bounds__(kMaxThreads)
@@ -276,19 +277,17 @@ batch_part_scatter_kernel(const MemberDev *__restrict__ members, const TileDev *
 }
 
 __global__ void __launch_bounds__(1024)
-batch_part_accum_kernel(const MemberDev *__restrict__ members, const BucketDev *__restrict__ buckets)
+batch_part_accum_kernel(const MemberDev *__restrict__ members, const ChunkDev *__restrict__ chunks)
 {
     extern __shared__ __align__(16) char smem[];
-    const BucketDev bk = buckets[blockIdx.x];
-    const MemberDev &M = members[bk.member];
-    const int64_t g0 = (int64_t)bk.bucket << M.bshift;
-    const int64_t bw = (int64_t)1 << M.bshift;
-    const int len = (int)((M.T - g0) < bw ? (M.T - g0) : bw);
-    const uint32_t r0 = M.bucket_start[bk.bucket], r1 = M.bucket_start[bk.bucket + 1];
+    const ChunkDev ck = chunks[blockIdx.x];
+    const MemberDev &M = members[ck.member];
     if (M.w)
-        part_accum<true>(M.rec_off, M.rec_w, r0, r1, g0, len, M.cnt, M.sumw, M.sumw2, smem);
+        part_accum_chunk<true>(ck.chunk, M.bucket_start, M.chunk_start, M.nbuckets, M.bshift, M.T,
+                               M.rec_off, M.rec_w, M.cnt, M.sumw, M.sumw2, smem);
     else
-        part_accum<false>(M.rec_off, M.rec_w, r0, r1, g0, len, M.cnt, M.sumw, M.sumw2, smem);
+        part_accum_chunk<false>(ck.chunk, M.bucket_start, M.chunk_start, M.nbuckets, M.bshift, M.T,
+                                M.rec_off, M.rec_w, M.cnt, M.sumw, M.sumw2, smem);
 }
 
 __global__ void zero_u32_kernel(uint32_t *p, int n)
@@ -312,10 +311,10 @@ struct hist_batch_s {
     int blocks = 1, threads = 1024;
     int lds = 0, lds_win = 0;
     // partitioned members
-    int npart = 0, nptiles = 0, nbuckets = 0;
+    int npart = 0, nptiles = 0, nchunks = 0;
     int32_t *d_part_members = nullptr;
     TileDev *d_ptiles = nullptr;
-    BucketDev *d_buckets = nullptr;
+    ChunkDev *d_chunks = nullptr;
     void *d_part = nullptr;
     int scatter_lds = 0, accum_lds = 0;
     hipStream_t cap_stream = nullptr;
@@ -343,8 +342,8 @@ static void batch_free(hist_batch_s *b)
         (void)hipFree(b->d_part_members);
     if (b->d_ptiles)
         (void)hipFree(b->d_ptiles);
-    if (b->d_buckets)
-        (void)hipFree(b->d_buckets);
+    if (b->d_chunks)
+        (void)hipFree(b->d_chunks);
     if (b->d_part)
         (void)hipFree(b->d_part);
     delete b;
@@ -361,8 +360,8 @@ static hipError_t batch_enqueue(hist_batch_s *b, hipStream_t s)
                        b->d_part_members);
     hipLaunchKernelGGL(batch_part_scatter_kernel, dim3(b->nptiles), dim3(1024), (size_t)b->scatter_lds,
                        s, b->d_members, b->d_ptiles);
-    hipLaunchKernelGGL(batch_part_accum_kernel, dim3(b->nbuckets), dim3(1024), (size_t)b->accum_lds,
-                       s, b->d_members, b->d_buckets);
+    hipLaunchKernelGGL(batch_part_accum_kernel, dim3(b->nchunks), dim3(1024), (size_t)b->accum_lds,
+                       s, b->d_members, b->d_chunks);
     return hipGetLastError();
 }
 
@@ -417,7 +416,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     std::vector<MemberDev> mem((size_t)k);
     std::vector<TileDev> tiles, ptiles;
     std::vector<int32_t> part_members;
-    std::vector<BucketDev> buckets;
+    std::vector<ChunkDev> chunks;
     std::vector<size_t> part_off((size_t)k, 0);   // scratch offsets of kAccPart members
     size_t part_bytes = 0;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
@@ -472,10 +471,12 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
             part_off[(size_t)i] = part_bytes;
             part_bytes += up((size_t)d.n * 4) + up((size_t)d.n * 2) +
                           (d.weights ? up((size_t)d.n * 8) : 0) +
-                          up((size_t)pnb * m.ntiles * 4) + up((size_t)(pnb + 1) * 4);
+                          up((size_t)pnb * m.ntiles * 4) + 2 * up((size_t)(pnb + 1) * 4);
             part_members.push_back(i);
-            for (int64_t j = 0; j < pnb; ++j)
-                buckets.push_back(BucketDev{i, (int32_t)j});
+            // every bucket has at most ceil(records / kPartChunk) chunks
+            const int64_t cmax = pnb + (d.n + kPartChunk - 1) / kPartChunk;
+            for (int64_t t = 0; t < cmax; ++t)
+                chunks.push_back(ChunkDev{i, (int32_t)t});
         } else {
             m.acc = kAccGlobal;
             m.win_len = 0;
@@ -503,7 +504,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     }
     b->npart = (int)part_members.size();
     b->nptiles = (int)ptiles.size();
-    b->nbuckets = (int)buckets.size();
+    b->nchunks = (int)chunks.size();
     std::stable_sort(tiles.begin(), tiles.end(),
                      [](const TileDev &x, const TileDev &y) { return x.len > y.len; });
     b->ntiles = (int)tiles.size();
@@ -520,7 +521,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         if (e == hipSuccess)
             e = hipMalloc(&b->d_ptiles, sizeof(TileDev) * ptiles.size());
         if (e == hipSuccess)
-            e = hipMalloc(&b->d_buckets, sizeof(BucketDev) * buckets.size());
+            e = hipMalloc(&b->d_chunks, sizeof(ChunkDev) * chunks.size());
         if (e == hipSuccess)
             e = hipMemcpy(b->d_part_members, part_members.data(), sizeof(int32_t) * part_members.size(),
                           hipMemcpyHostToDevice);
@@ -528,7 +529,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
             e = hipMemcpy(b->d_ptiles, ptiles.data(), sizeof(TileDev) * ptiles.size(),
                           hipMemcpyHostToDevice);
         if (e == hipSuccess)
-            e = hipMemcpy(b->d_buckets, buckets.data(), sizeof(BucketDev) * buckets.size(),
+            e = hipMemcpy(b->d_chunks, chunks.data(), sizeof(ChunkDev) * chunks.size(),
                           hipMemcpyHostToDevice);
         if (e == hipSuccess) {
             for (int i : part_members) {
@@ -546,6 +547,8 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
                 m.table = reinterpret_cast<uint32_t *>(q);
                 q += up((size_t)m.nbuckets * m.ntiles * 4);
                 m.bucket_start = reinterpret_cast<uint32_t *>(q);
+                q += up((size_t)(m.nbuckets + 1) * 4);
+                m.chunk_start = reinterpret_cast<uint32_t *>(q);
             }
         }
         if (e == hipSuccess)

@@ -78,8 +78,10 @@ uint64_t hg::host_order_key(double x)
 static bool is_capturing(hipStream_t s)
 {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
-    if (hipStreamIsCapturing(s, &st) != hipSuccess)
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) {
+        (void)hipGetLastError();   // leave no stale error for the next launch check
         return false;
+    }
     return st != hipStreamCaptureStatusNone;
 }
 
@@ -94,8 +96,8 @@ static hipError_t dalloc(T **p, size_t count)
 
 static void dfree(void *p)
 {
-    if (p)
-        (void)hipFree(p);
+    if (p && hipFree(p) != hipSuccess)
+        (void)hipGetLastError();
 }
 
 static void free_handle(hist_s *h)
@@ -279,7 +281,7 @@ hist_status hg::ensure_stage(hist_s *h, size_t bytes, hipStream_t s)
     if (e != hipSuccess)
         return set_error(HIST_ENOMEM, "staging buffer of %zu bytes: %s", bytes, hipGetErrorString(e));
     if (h->d_stage) {
-        (void)hipStreamSynchronize(s);
+        HIPCHK(hipStreamSynchronize(s), "synchronize before freeing scratch");
         dfree(h->d_stage);
     }
     h->d_stage = p;
@@ -299,9 +301,8 @@ hist_status hg::ensure_gbins(hist_s *h, int64_t count, hipStream_t s)
     if (e != hipSuccess)
         return set_error(HIST_ENOMEM, "tile scratch: %s", hipGetErrorString(e));
     if (h->d_gbins) {
-        (void)hipStreamSynchronize(s);
+        HIPCHK(hipStreamSynchronize(s), "synchronize before freeing scratch");
         dfree(h->d_gbins);
-    dfree(h->d_part);
     }
     h->d_gbins = p;
     h->gbins_cap = count;
@@ -321,7 +322,7 @@ static hist_status ensure_part(hist_s *h, size_t bytes, hipStream_t s)
         return set_error(HIST_ENOMEM, "partition scratch of %zu bytes: %s", bytes,
                          hipGetErrorString(e));
     if (h->d_part) {
-        (void)hipStreamSynchronize(s);
+        HIPCHK(hipStreamSynchronize(s), "synchronize before freeing scratch");
         dfree(h->d_part);
     }
     h->d_part = p;
@@ -341,7 +342,7 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
     const int nb = (int)((h->T + ((int64_t)1 << b) - 1) >> b);
     const int G = p.blocks;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t table_b = up((size_t)nb * G * 4), start_b = up((size_t)(nb + 1) * 4);
+    const size_t table_b = up((size_t)nb * G * 4), start_b = 2 * up((size_t)(nb + 1) * 4);
     const size_t off_b = up((size_t)mmax * 2), w_b = weighted ? up((size_t)mmax * 8) : 0;
     hist_status st = ensure_gbins(h, mmax, s);
     if (st != HIST_OK)
@@ -354,6 +355,7 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
     std::memset(&P, 0, sizeof(P));
     P.table = reinterpret_cast<uint32_t *>(base);
     P.bucket_start = reinterpret_cast<uint32_t *>(base + table_b);
+    P.chunk_start = reinterpret_cast<uint32_t *>(base + table_b + start_b / 2);
     P.rec_off = reinterpret_cast<uint16_t *>(base + table_b + start_b);
     P.rec_w = weighted ? reinterpret_cast<double *>(base + table_b + start_b + off_b) : nullptr;
     P.T = h->T;
@@ -382,7 +384,10 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
         HIPCHK(launch_part_scan(P, g, s), "partition scan launch");
         HIPCHK(launch_part_scatter(f32, weighted, p.threads, g, (size_t)p.lds, c, P, s),
                "partition scatter launch");
-        HIPCHK(launch_part_accum(weighted, 1024, acc_lds, c, P, s), "partition accumulate launch");
+        // every bucket has at most ceil(records / kPartChunk) chunks
+        const int chunks_max = nb + (int)((m + kPartChunk - 1) / kPartChunk);
+        HIPCHK(launch_part_accum(weighted, 1024, chunks_max, acc_lds, c, P, s),
+               "partition accumulate launch");
     }
     const int t1 = h->timing ? timing_event(h) : -1;
     if (t0 >= 0 && t1 >= 0) {
@@ -491,6 +496,9 @@ FillArgs hg::base_args(const hist_s *h, const void *const *coords, const void *w
 hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, const void *w,
                          int64_t n, hist_dtype dtype, hipStream_t s)
 {
+    // launches are checked with hipGetLastError: start from a clean state, so
+    // an error left by an unrelated runtime call is not reported as ours
+    (void)hipGetLastError();
     const bool f32 = dtype == HIST_F32;
     const bool weighted = w != nullptr;
     FillArgs a = base_args(h, coords, w, n);

@@ -89,6 +89,7 @@ struct TileArgs {
 struct PartArgs {
     uint32_t *table;          // [nbuckets * G] counts per (bucket, workgroup), then first slots
     uint32_t *bucket_start;   // [nbuckets + 1] first slot of every bucket, then the total
+    uint32_t *chunk_start;    // [nbuckets + 1] first accumulate chunk of every bucket, then the count
     uint16_t *rec_off;        // [m] bin offset within the bucket, in bucket order
     double *rec_w;            // [m] weights in bucket order (weighted fills)
     int64_t T;                // total bins
@@ -97,6 +98,11 @@ struct PartArgs {
     int32_t lds_buckets;      // byte offset of the per-bucket counters in LDS
     int32_t pad;
 };
+
+// Records one accumulate workgroup of the partitioned strategy takes: a bucket
+// with more records is split into chunks of this many, each added in its own
+// LDS copy and merged with coalesced atomics.
+constexpr uint32_t kPartChunk = 65536;
 
 // Raises a kernel's dynamic LDS limit to the whole 160 KB (once per kernel).
 void allow_big_lds_ptr(const void *kernel);
@@ -116,8 +122,8 @@ hipError_t launch_part_count(int dims, bool f32, bool weighted, int threads, int
 hipError_t launch_part_scan(const PartArgs &p, int blocks, hipStream_t s);
 hipError_t launch_part_scatter(bool f32, bool weighted, int threads, int blocks, size_t lds,
                                const FillArgs &a, const PartArgs &p, hipStream_t s);
-hipError_t launch_part_accum(bool weighted, int threads, size_t lds, const FillArgs &a,
-                             const PartArgs &p, hipStream_t s);
+hipError_t launch_part_accum(bool weighted, int threads, int blocks, size_t lds,
+                             const FillArgs &a, const PartArgs &p, hipStream_t s);
 hipError_t launch_zero_u64(uint64_t *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t n, hipStream_t s);
 hipError_t launch_add_u64_to_f64(double *dst, const uint64_t *src, int64_t n, hipStream_t s);

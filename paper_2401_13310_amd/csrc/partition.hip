@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(kMaxThreads) part_count_kernel(const FillArgs 
 
 __global__ void __launch_bounds__(1024) part_scan_kernel(PartArgs P, int G)
 {
-    part_scan(P.table, P.bucket_start, P.nbuckets, G);
+    part_scan(P.table, P.bucket_start, P.chunk_start, P.nbuckets, G);
 }
 
 template <typename T, bool W>
@@ -80,12 +80,8 @@ template <bool W>
 __global__ void __launch_bounds__(1024) part_accum_kernel(const FillArgs A, PartArgs P)
 {
     extern __shared__ __align__(16) char smem[];
-    const int j = blockIdx.x;
-    const int64_t g0 = (int64_t)j << P.bshift;
-    const int64_t bw = (int64_t)1 << P.bshift;
-    const int len = (int)((P.T - g0) < bw ? (P.T - g0) : bw);
-    part_accum<W>(P.rec_off, P.rec_w, P.bucket_start[j], P.bucket_start[j + 1], g0, len, A.cnt,
-                  A.sumw, A.sumw2, smem);
+    part_accum_chunk<W>(blockIdx.x, P.bucket_start, P.chunk_start, P.nbuckets, P.bshift, P.T,
+                        P.rec_off, P.rec_w, A.cnt, A.sumw, A.sumw2, smem);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -146,17 +142,17 @@ hipError_t launch_part_scatter(bool f32, bool weighted, int threads, int blocks,
     return launch_ps<double, true>(threads, blocks, lds, a, p, s);
 }
 
-hipError_t launch_part_accum(bool weighted, int threads, size_t lds, const FillArgs &a,
-                             const PartArgs &p, hipStream_t s)
+hipError_t launch_part_accum(bool weighted, int threads, int blocks, size_t lds,
+                             const FillArgs &a, const PartArgs &p, hipStream_t s)
 {
     if (weighted) {
         auto k = part_accum_kernel<true>;
         allow_big_lds_ptr(reinterpret_cast<const void *>(k));
-        hipLaunchKernelGGL(k, dim3(p.nbuckets), dim3(threads), lds, s, a, p);
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a, p);
     } else {
         auto k = part_accum_kernel<false>;
         allow_big_lds_ptr(reinterpret_cast<const void *>(k));
-        hipLaunchKernelGGL(k, dim3(p.nbuckets), dim3(threads), lds, s, a, p);
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a, p);
     }
     return hipGetLastError();
 }

@@ -504,8 +504,12 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
         if (p.strategy != c.strategy)
             continue;
         st = run_plan(h, p, coords, weights, n, dtype, s);   // warm-up (and allocations)
-        if (st != HIST_OK)
+        if (st != HIST_OK) {
+            if (std::getenv("HIST_LOG"))
+                fprintf(stderr, "hist_tune: candidate strategy %d bucket_bits %d failed: %s\n",
+                        c.strategy, c.bucket_bits, hist_last_error());
             continue;
+        }
         float tmin = 1e30f;
         for (int r = 0; r < 5; ++r) {
             (void)hipEventRecord(e0, s);

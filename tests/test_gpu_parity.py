@@ -233,6 +233,29 @@ def test_fill_part_two_chunks(hg):
     fill_and_compare(hg, axes, coords, None, strategy=hg.HIST_STRAT_PART)
 
 
+def test_fill_scratch_regrowth_across_strategies(hg):
+    """One handle alternates the partitioned and tiled strategies with growing
+    and shrinking fills, so their scratch buffers are reallocated in between;
+    every fill adds to the same histogram."""
+    import torch
+    rng = np.random.default_rng(44)
+    axes = [{"nbins": 400, "xmin": -3.0, "xmax": 3.0}, {"nbins": 500, "xmin": -3.0, "xmax": 3.0}]
+    h = hg.Hist(axes)
+    o = oracle.Oracle(axes)
+    for strat, n in [(hg.HIST_STRAT_PART, 300_000), (hg.HIST_STRAT_TILED, 900_000),
+                     (hg.HIST_STRAT_PART, 200_000), (hg.HIST_STRAT_PART, 1_200_000),
+                     (hg.HIST_STRAT_TILED, 100_000)]:
+        coords = [rng.normal(0, 1, n), rng.normal(0, 1, n)]
+        h.set_strategy(strat, 0, 0)
+        h.fill([dev(c) for c in coords], None)
+        o.fill(coords, None)
+    sumw, _, entries = h.read()
+    osw, _, _, oent = o.read()
+    assert entries == oent
+    assert_bins_equal(sumw, osw, "counts after regrowth")
+    torch.cuda.synchronize()
+
+
 def test_fill_part_sparse(hg):
     rng = np.random.default_rng(43)
     axes = [{"nbins": 1_000_000, "xmin": 0.0, "xmax": 1.0}]
