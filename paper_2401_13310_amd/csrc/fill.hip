@@ -31,6 +31,8 @@ __device__ __forceinline__ int window_words(int acc, int win_len, int copies)
 {
     if (acc == ACC_U32)
         return win_len * copies;
+    if (acc == ACC_PCOUNT)
+        return win_len;
     if (acc == ACC_U16)
         return (win_len + 1) >> 1;
     return win_len * copies * 4;   // F64: 2 doubles, F32C: 4 floats per bin and copy
@@ -60,7 +62,11 @@ __device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A)
 {
     const int W = A.win_len;
     const int C = A.copies;
-    if (ACC == ACC_U32) {
+    if (ACC == ACC_PCOUNT) {
+        // this block's column of the bucket-major count table
+        for (int j = threadIdx.x; j < W; j += blockDim.x)
+            A.part_table[(int64_t)j * gridDim.x + blockIdx.x] = win[j];
+    } else if (ACC == ACC_U32) {
         if (A.merge == MERGE_STAGE) {
             uint32_t *st = static_cast<uint32_t *>(A.stage) + (int64_t)blockIdx.x * A.stage_stride;
             for (int l = threadIdx.x; l < W; l += blockDim.x) {
@@ -244,7 +250,7 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
                                               const T (&cx)[U][D], const T (&cw)[U],
                                               uint32_t base, uint32_t len, int cp,
                                               double (&st)[NStats<D>::v], uint32_t &nin,
-                                              Prefetch &&prefetch)
+                                              int32_t *gb, Prefetch &&prefetch)
 {
     constexpr int KIND = kind_of_set<KS>();
     constexpr bool early = KIND == AX_UNIFORM;
@@ -304,9 +310,14 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
             nin += take ? 1u : 0u;
         }
         const uint32_t l = (uint32_t)(g - A.win_lo);
-        out[j] = ok && !(l < wlen);
+        out[j] = ACC != ACC_PCOUNT && ok && !(l < wlen);
         any_out = any_out || out[j];
-        if (ok && l < wlen) {
+        if (ACC == ACC_PCOUNT) {
+            if (ok) {
+                gb[base + (uint32_t)j * blockDim.x + threadIdx.x] = g;
+                lds_add_u32(&win[(uint32_t)g >> A.part_shift], 1u);
+            }
+        } else if (ok && l < wlen) {
             if (ACC == ACC_U32) {
                 lds_add_u32(&win[__umul24(l, (uint32_t)A.copies) + cp], 1u);
             } else if (ACC == ACC_U16) {
@@ -391,12 +402,13 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
         xb[a] = column_rsrc(static_cast<const T *>(A.coords[a]) + start, bytes);
     const __amdgpu_buffer_rsrc_t wb =
         column_rsrc(W ? static_cast<const T *>(A.w) + start : static_cast<const T *>(A.coords[0]), W ? bytes : 0u);
+    int32_t *gb = ACC == ACC_PCOUNT ? A.gbins + start : nullptr;
     T cx[U][D], cw[U];
     if (len > 0)
         load_batch<D, T, W, U>(xb, wb, 0, cx, cw);
     for (uint32_t base = 0; base < len; base += step) {
         T nx[U][D], nw[U];
-        process_batch<D, T, ACC, W, U, KS>(A, smem, win, cx, cw, base, len, cp, st, nin, [&] {
+        process_batch<D, T, ACC, W, U, KS>(A, smem, win, cx, cw, base, len, cp, st, nin, gb, [&] {
             load_batch<D, T, W, U>(xb, wb, base + step, nx, nw);
         });
         if (ACC == ACC_U16 && ++it == A.epoch_iters) {
@@ -668,6 +680,9 @@ template <int D, typename T, int KS>
 static hipError_t launch_fill_k(int acc, bool weighted, int threads, int blocks, size_t lds,
                                 const FillArgs &a, hipStream_t s)
 {
+    if (acc == ACC_PCOUNT)
+        return weighted ? launch_fill_t<D, T, ACC_PCOUNT, true, KS>(threads, blocks, lds, a, s)
+                        : launch_fill_t<D, T, ACC_PCOUNT, false, KS>(threads, blocks, lds, a, s);
     if (!weighted) {
         if (acc == ACC_U32)
             return launch_fill_t<D, T, ACC_U32, false, KS>(threads, blocks, lds, a, s);

@@ -375,11 +375,19 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
             c.coords[d] = static_cast<const char *>(coords[d]) + off * esz;
         c.w = w ? static_cast<const char *>(w) + off * esz : nullptr;
         c.n = m;
+        const int64_t step = (int64_t)p.threads * unroll_of(h->dims, f32, weighted);
         int64_t per = (m + G - 1) / G;
-        per = (per + p.threads - 1) / p.threads * p.threads;
+        per = (per + step - 1) / step * step;
         const int g = (int)((m + per - 1) / per);
         c.per_block = per;
-        HIPCHK(launch_part_count(h->dims, f32, weighted, p.threads, g, (size_t)p.lds, c, P, s),
+        // count pass: the fill kernel in its partition-count mode
+        c.win_lo = 0;
+        c.win_len = nb;
+        c.copies = 1;
+        c.lds_win = p.lds_base;
+        c.part_table = P.table;
+        c.part_shift = b;
+        HIPCHK(launch_fill(h->dims, f32, ACC_PCOUNT, weighted, p.threads, g, (size_t)p.lds, c, s),
                "partition count launch");
         HIPCHK(launch_part_scan(P, g, s), "partition scan launch");
         HIPCHK(launch_part_scatter(f32, weighted, p.threads, g, (size_t)p.lds, c, P, s),

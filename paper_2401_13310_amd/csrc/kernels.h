@@ -12,7 +12,9 @@ enum Acc : int32_t {
     ACC_U16 = 1,   // unit weights: 16-bit counters packed in pairs, drained by
                    // periodic scans so they provably never overflow
     ACC_F64 = 2,   // weights: binary64 sum and sum of squares, `copies` copies
-    ACC_F32C = 3   // FP32 weights: FP32 sums with TwoSum compensation terms
+    ACC_F32C = 3,  // FP32 weights: FP32 sums with TwoSum compensation terms
+    ACC_PCOUNT = 4 // count pass of the partitioned strategy: global bins to
+                   // scratch and per-bucket event counts (win_len buckets)
 };
 
 enum Merge : int32_t { MERGE_ATOMIC = 0, MERGE_STAGE = 1 };
@@ -66,7 +68,10 @@ struct FillArgs {
     double *stats;            // [S]
     void *stage;              // staging, one slot of stage_stride units per block
     int64_t stage_stride;     // units per block: u32 words (U32/U16) or bins (F64/F32C)
-    int32_t *gbins;           // TILED pass 1: global bin of every event
+    int32_t *gbins;           // TILED pass 1 / PCOUNT: global bin of every event
+    uint32_t *part_table;     // PCOUNT: bucket-major counts table[bucket * gridDim.x + block]
+    int32_t part_shift;       // PCOUNT: log2 of the bucket width
+    int32_t pad0;
 };
 
 struct TileArgs {
@@ -117,8 +122,6 @@ hipError_t launch_tiled_bins(int dims, bool f32, bool weighted, int threads, int
                              size_t lds, const FillArgs &a, hipStream_t s);
 hipError_t launch_tile(int acc, bool f32, int threads, int blocks_x, int tiles, size_t lds,
                        const TileArgs &t, hipStream_t s);
-hipError_t launch_part_count(int dims, bool f32, bool weighted, int threads, int blocks, size_t lds,
-                             const FillArgs &a, const PartArgs &p, hipStream_t s);
 hipError_t launch_part_scan(const PartArgs &p, int blocks, hipStream_t s);
 hipError_t launch_part_scatter(bool f32, bool weighted, int threads, int blocks, size_t lds,
                                const FillArgs &a, const PartArgs &p, hipStream_t s);
