@@ -20,14 +20,6 @@ __device__ __forceinline__ void lds_add_f64(double *p, double v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ float lds_add_rtn_f32(float *p, float v)
-{
-    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_add_f32(float *p, float v)
-{
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
 __device__ __forceinline__ void gl_add_u64(uint64_t *p, uint64_t v)
 {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -47,6 +39,29 @@ __device__ __forceinline__ float two_sum_err(float a, float b)
     float bp = s - a;
     float ap = s - bp;
     return (a - ap) + (b - bp);
+}
+
+// Compensated FP32 addition of v (plus an exact extra error term) into a
+// (sum, compensation) pair kept as one 64-bit LDS word, sum in the low half:
+// sum' = fl(sum + v), comp' = fl(comp + (err(sum + v) + extra)), with the
+// TwoSum error err.  `old` is the pair as last read; a compare-and-swap makes
+// the pair update atomic and is retried with the word it found when another
+// lane changed the pair first.
+__device__ __forceinline__ void lds_add_compensated(uint64_t *p, uint64_t old, float v, float extra)
+{
+#pragma clang fp contract(off)
+    for (;;) {
+        const float s = __uint_as_float((uint32_t)old);
+        const float c = __uint_as_float((uint32_t)(old >> 32));
+        const float ns = s + v;
+        const float nc = c + (two_sum_err(s, v) + extra);
+        const uint64_t nw = (uint64_t)__float_as_uint(ns) | ((uint64_t)__float_as_uint(nc) << 32);
+        uint64_t expected = old;
+        if (__hip_atomic_compare_exchange_strong(p, &expected, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP))
+            return;
+        old = expected;
+    }
 }
 
 // Per-event statistics terms, rounded in the order w, w*w, w*x, (w*x)*x,

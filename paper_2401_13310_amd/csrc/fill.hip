@@ -101,7 +101,8 @@ __device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A)
             }
         }
     } else {
-        // F64: [sumw][sumw2] each W*C doubles; F32C: [sw][cw][sw2][cw2] each W*C floats
+        // F64: [sumw][sumw2] each W*C doubles; F32C: [(sw, cw)][(sw2, cw2)] each
+        // W*C pairs of floats (sum in the low word, compensation in the high)
         const int n1 = W * C;
         for (int l = threadIdx.x; l < W; l += blockDim.x) {
             double s = 0.0, s2 = 0.0;
@@ -112,10 +113,11 @@ __device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A)
                     s2 += d[n1 + l * C + r];
                 }
             } else {
-                const float *f = reinterpret_cast<const float *>(win);
+                const uint64_t *q = reinterpret_cast<const uint64_t *>(win);
                 for (int r = 0; r < C; ++r) {
-                    s += (double)f[l * C + r] + (double)f[n1 + l * C + r];
-                    s2 += (double)f[2 * n1 + l * C + r] + (double)f[3 * n1 + l * C + r];
+                    const uint64_t a = q[l * C + r], b = q[n1 + l * C + r];
+                    s += (double)__uint_as_float((uint32_t)a) + (double)__uint_as_float((uint32_t)(a >> 32));
+                    s2 += (double)__uint_as_float((uint32_t)b) + (double)__uint_as_float((uint32_t)(b >> 32));
                 }
             }
             if (A.merge == MERGE_STAGE) {
@@ -273,9 +275,7 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
 #pragma unroll
     for (int a = 0; a < D; ++a)
         axis_bins_finish<U, KIND>(x[a], A.ax[a], lo[a], hi[a], ev[a], b[a]);
-    // compensated FP32: returning LDS adds of the whole batch are issued
-    // before any of their results is used, so their latencies overlap
-    float o1[U], o2[U], wfv[U], w2v[U], e2v[U];
+    float wfv[U], w2v[U], e2v[U];
     uint32_t fidx[U];
     bool fin[U];
     int32_t gv[U];
@@ -328,29 +328,35 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
                 lds_add_f64(&s[idx], w);
                 lds_add_f64(&s[wlen * A.copies + idx], w * w);
             } else {
-                float *s = reinterpret_cast<float *>(win);
-                const uint32_t n1 = wlen * A.copies;
-                const uint32_t idx = __umul24(l, (uint32_t)A.copies) + cp;
                 const float wf = (float)cw[j];
                 const float w2 = wf * wf;
                 wfv[j] = wf;
                 w2v[j] = w2;
                 e2v[j] = __builtin_fmaf(wf, wf, -w2);   // exact: wf*wf = w2 + e2
-                fidx[j] = idx;
+                fidx[j] = __umul24(l, (uint32_t)A.copies) + cp;
                 fin[j] = true;
-                o1[j] = lds_add_rtn_f32(&s[idx], wf);
-                o2[j] = lds_add_rtn_f32(&s[2 * n1 + idx], w2);
             }
         }
     }
     if (ACC == ACC_F32C) {
-        float *s = reinterpret_cast<float *>(win);
+        // each (sum, compensation) pair is updated as one 64-bit word: the
+        // reads of the whole batch are issued first, then one compare-and-swap
+        // per pair, repeated only when another lane changed the pair in between
+        uint64_t *q = reinterpret_cast<uint64_t *>(win);
         const uint32_t n1 = wlen * A.copies;
+        uint64_t old1[U], old2[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             if (fin[j]) {
-                lds_add_f32(&s[n1 + fidx[j]], two_sum_err(o1[j], wfv[j]));
-                lds_add_f32(&s[3 * n1 + fidx[j]], two_sum_err(o2[j], w2v[j]) + e2v[j]);
+                old1[j] = q[fidx[j]];
+                old2[j] = q[n1 + fidx[j]];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            if (fin[j]) {
+                lds_add_compensated(&q[fidx[j]], old1[j], wfv[j], 0.0f);
+                lds_add_compensated(&q[n1 + fidx[j]], old2[j], w2v[j], e2v[j]);
             }
         }
     }
@@ -670,7 +676,7 @@ template <int D, typename T, int ACC, bool W, int KS>
 static hipError_t launch_fill_t(int threads, int blocks, size_t lds, const FillArgs &a,
                                 hipStream_t s)
 {
-    auto k = fill_kernel<D, T, ACC, W, fill_unroll(D, sizeof(T) == 4, W), KS>;
+    auto k = fill_kernel<D, T, ACC, W, fill_unroll(D, sizeof(T) == 4, W, ACC, KS), KS>;
     allow_big_lds(k);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a);
     return hipGetLastError();
@@ -714,23 +720,11 @@ static hipError_t launch_fill_d(int acc, bool weighted, int ks, int threads, int
     }
 }
 
-// Kernel specialization for the axis kinds of a fill.
-static int kind_set(int dims, const FillArgs &a)
-{
-    bool all_uniform = true;
-    for (int d = 0; d < dims; ++d)
-        all_uniform = all_uniform && a.ax[d].kind == AX_UNIFORM;
-    if (all_uniform)
-        return KS_UNIFORM;
-    if (dims == 1)
-        return a.ax[0].kind == AX_LEARNED ? KS_LEARNED1 : KS_BSEARCH1;
-    return KS_MIXED;
-}
 
 hipError_t launch_fill(int dims, bool f32, int acc, bool weighted, int threads, int blocks,
                        size_t lds, const FillArgs &a, hipStream_t s)
 {
-    const int ks = kind_set(dims, a);
+    const int ks = kind_set(dims, a.ax);
     switch (dims * 2 + (f32 ? 1 : 0)) {
     case 2: return launch_fill_d<1, double>(acc, weighted, ks, threads, blocks, lds, a, s);
     case 3: return launch_fill_d<1, float>(acc, weighted, ks, threads, blocks, lds, a, s);

@@ -375,7 +375,7 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
             c.coords[d] = static_cast<const char *>(coords[d]) + off * esz;
         c.w = w ? static_cast<const char *>(w) + off * esz : nullptr;
         c.n = m;
-        const int64_t step = (int64_t)p.threads * unroll_of(h->dims, f32, weighted);
+        const int64_t step = (int64_t)p.threads * unroll_of(h, f32, weighted, ACC_PCOUNT);
         int64_t per = (m + G - 1) / G;
         per = (per + step - 1) / step * step;
         const int g = (int)((m + per - 1) / per);

@@ -43,10 +43,26 @@ constexpr int kTileUnroll = 4;
 
 // Events each thread loads per loop iteration of the fill kernel.
 // Sized so the double-buffered batch fits the 128 VGPRs a 1024-thread
-// workgroup allows without spilling.
-__host__ __device__ constexpr int fill_unroll(int D, bool f32, bool weighted)
+// workgroup allows without spilling; kernels that dispatch on the axis kinds
+// at run time (KS_MIXED) carry every kind's code and get fewer events.
+__host__ __device__ constexpr int fill_unroll(int D, bool f32, bool weighted, int acc, int ks)
 {
-    return D == 1 ? ((weighted && !f32) ? 4 : 8) : (D == 2 ? 4 : 2);
+    return ks == KS_MIXED ? (D == 2 && acc != ACC_F32C ? 2 : 1)
+                          : (acc == ACC_F32C ? 4
+                                             : (D == 1 ? ((weighted && !f32) ? 4 : 8) : (D == 2 ? 4 : 2)));
+}
+
+// Kernel specialization for the axis kinds of a fill.
+__host__ __device__ inline int kind_set(int dims, const AxisDev *ax)
+{
+    bool all_uniform = true;
+    for (int d = 0; d < dims; ++d)
+        all_uniform = all_uniform && ax[d].kind == AX_UNIFORM;
+    if (all_uniform)
+        return KS_UNIFORM;
+    if (dims == 1)
+        return ax[0].kind == AX_LEARNED ? KS_LEARNED1 : KS_BSEARCH1;
+    return KS_MIXED;
 }
 
 struct FillArgs {

@@ -104,6 +104,6 @@ int64_t tiled_chunk(const hist_s *h);
 int64_t part_chunk(const hist_s *h);
 // Smallest and largest log2 bucket width a PART plan can use (lo > hi: none).
 void part_bits_range(const hist_s *h, bool weighted, int lds_base, int &lo, int &hi);
-int unroll_of(int dims, bool f32, bool weighted);
+int unroll_of(const hist_s *h, bool f32, bool weighted, int acc);
 
 }  // namespace hg

@@ -20,7 +20,10 @@
 
 namespace hg {
 
-int unroll_of(int dims, bool f32, bool weighted) { return fill_unroll(dims, f32, weighted); }
+int unroll_of(const hist_s *h, bool f32, bool weighted, int acc)
+{
+    return fill_unroll(h->dims, f32, weighted, acc, kind_set(h->dims, h->ax));
+}
 
 int apply_model_offsets(const hist_s *h, FillArgs &a)
 {
@@ -191,7 +194,7 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
         p.lds = p.lds_base + window_bytes(acc, len, copies);
     }
 
-    const int U = fill_unroll(h->dims, f32, weighted);
+    const int U = unroll_of(h, f32, weighted, p.acc);
     const int64_t step = (int64_t)p.threads * U;
     int bpc = c.blocks_per_cu > 0 ? c.blocks_per_cu : (p.lds > h->lds_max / 2 ? 1 : 2);
     if (p.lds * bpc > h->lds_max)
