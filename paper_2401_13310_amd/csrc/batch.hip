@@ -12,6 +12,7 @@
 // copy and statistics with atomics -- tiles of one member run concurrently on
 // several CUs.  The last workgroup to finish resets the queue, so the graph
 // holds a single kernel node and replays need no memset.
+#include "fill_body.h"
 #include "part_common.h"
 #include "plan.h"
 
@@ -59,100 +60,64 @@ struct ChunkDev {
     int32_t chunk;                // accumulate chunk of the member (may be past its last)
 };
 
-// Events [start, start+len) of member M: find bin, statistics, accumulation.
-template <bool F32, bool W>
-__device__ void batch_events(const MemberDev &M, int64_t start, int32_t len, const char *smem,
-                             uint32_t *win, double (&st)[kMaxStats])
+// A member's fill variant: dims, input type, accumulation (unit-weight LDS
+// counts, binary64 LDS sums, or the partition count pass with or without
+// weights) and axis kinds.
+enum BatchAcc : int32_t { BA_U32 = 0, BA_F64 = 1, BA_PCOUNT = 2, BA_PCOUNT_W = 3 };
+
+__host__ __device__ constexpr int batch_variant(int dims, bool f32, int bacc, int ks)
 {
-    using T = typename std::conditional<F32, float, double>::type;
-    const int dims = M.dims;
-    const int nthr = blockDim.x, tid = threadIdx.x;
-    const int C = M.copies;
-    const int cp = tid % C;
-    const uint32_t wlen = M.acc >= 0 ? (uint32_t)M.win_len : 0u;
-    constexpr int U = 2;
-    for (int32_t base = 0; base < len; base += nthr * U) {
-        T xv[U][kMaxDims];
-        T wv[U];
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const int32_t i = base + j * nthr + tid;
-            const bool ok = i < len;
-            for (int a = 0; a < kMaxDims; ++a)
-                xv[j][a] = (ok && a < dims)
-                               ? __builtin_nontemporal_load(static_cast<const T *>(M.coords[a]) + start + i)
-                               : T(0);
-            wv[j] = (W && ok) ? __builtin_nontemporal_load(static_cast<const T *>(M.w) + start + i) : T(0);
-        }
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            if (base + j * nthr + tid >= len)
-                continue;
-            double x[kMaxDims] = {0.0, 0.0, 0.0};
-            int32_t g = 0;
-            bool inside = true;
-            for (int a = 0; a < dims; ++a) {
-                x[a] = (double)xv[j][a];
-                const int32_t b = axis_bin(x[a], M.ax[a], smem);
-                inside = inside && (uint32_t)(b - 1) < (uint32_t)M.ax[a].nbins;
-                g += (a == 0) ? b : b * M.ax[a].stride;
-            }
-            const double w = W ? (double)wv[j] : 1.0;
-            if (inside)
-                stats_add_rt(st, x, w, dims);
-            if ((uint32_t)g < wlen) {
-                if (W) {
-                    double *s = reinterpret_cast<double *>(win);
-                    const uint32_t idx = (uint32_t)g * C + cp;
-                    lds_add_f64(&s[idx], w);
-                    lds_add_f64(&s[wlen * C + idx], w * w);
-                } else {
-                    lds_add_u32(&win[(uint32_t)g * C + cp], 1u);
-                }
-            } else if (W) {
-                gl_add_f64(&M.sumw[g], w);
-                gl_add_f64(&M.sumw2[g], w * w);
-            } else {
-                gl_add_u64(&M.cnt[g], 1ull);
-            }
-        }
+    return (((dims - 1) * 2 + (f32 ? 1 : 0)) * 4 + bacc) * 4 + ks;
+}
+
+// One tile of one member: the fill body specialized for the member's variant.
+// Not inlined, so the persistent kernel stays small and each variant compiles
+// on its own; the call costs nothing next to a tile of tens of thousands of
+// events.
+template <int D, typename T, int ACC, bool W, int KS>
+__device__ __attribute__((noinline)) void batch_tile(const FillArgs *__restrict__ A, int64_t start,
+                                                     int64_t end, int col, int cols)
+{
+    extern __shared__ __align__(16) char smem[];
+    fill_range<D, T, ACC, W, fill_unroll(D, sizeof(T) == 4, W, ACC, KS), KS>(*A, smem, start, end, col,
+                                                                             cols);
+}
+
+template <int D, typename T, int KS>
+__device__ __forceinline__ void batch_tile_acc(int bacc, const FillArgs *A, int64_t start, int64_t end,
+                                               int col, int cols)
+{
+    switch (bacc) {
+    case BA_U32: batch_tile<D, T, ACC_U32, false, KS>(A, start, end, col, cols); break;
+    case BA_F64: batch_tile<D, T, ACC_F64, true, KS>(A, start, end, col, cols); break;
+    case BA_PCOUNT: batch_tile<D, T, ACC_PCOUNT, false, KS>(A, start, end, col, cols); break;
+    default: batch_tile<D, T, ACC_PCOUNT, true, KS>(A, start, end, col, cols); break;
     }
 }
 
-// Count pass of a kAccPart member's tile: global bins to the member's scratch,
-// statistics, and the tile's events per bucket in LDS (`cnt`).
-template <bool F32, bool W>
-__device__ void batch_count_events(const MemberDev &M, int64_t start, int32_t len, const char *smem,
-                                   uint32_t *cnt, double (&st)[kMaxStats])
+template <int D, typename T>
+__device__ __forceinline__ void batch_tile_ks(int bacc, int ks, const FillArgs *A, int64_t start,
+                                              int64_t end, int col, int cols)
 {
-    using T = typename std::conditional<F32, float, double>::type;
-    const int dims = M.dims;
-    const int nthr = blockDim.x, tid = threadIdx.x;
-    for (int32_t i = tid; i < len; i += nthr) {
-        double x[kMaxDims] = {0.0, 0.0, 0.0};
-        int32_t g = 0;
-        bool inside = true;
-        for (int a = 0; a < dims; ++a) {
-            x[a] = (double)__builtin_nontemporal_load(static_cast<const T *>(M.coords[a]) + start + i);
-            const int32_t b = axis_bin(x[a], M.ax[a], smem);
-            inside = inside && (uint32_t)(b - 1) < (uint32_t)M.ax[a].nbins;
-            g += (a == 0) ? b : b * M.ax[a].stride;
-        }
-        M.gbins[start + i] = g;
-        if (inside)
-            stats_add_rt(st, x, W ? (double)static_cast<const T *>(M.w)[start + i] : 1.0, dims);
-        lds_add_u32(&cnt[(uint32_t)g >> M.bshift], 1u);
+    if (ks == KS_UNIFORM) {
+        batch_tile_acc<D, T, KS_UNIFORM>(bacc, A, start, end, col, cols);
+    } else if constexpr (D == 1) {
+        if (ks == KS_LEARNED1)
+            batch_tile_acc<D, T, KS_LEARNED1>(bacc, A, start, end, col, cols);
+        else
+            batch_tile_acc<D, T, KS_BSEARCH1>(bacc, A, start, end, col, cols);
+    } else {
+        batch_tile_acc<D, T, KS_MIXED>(bacc, A, start, end, col, cols);
     }
 }
 
 __global__ void __launch_bounds__(kMaxThreads)
-batch_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ tiles, int ntiles,
-             uint32_t *queue, int lds_win)
+batch_kernel(const MemberDev *__restrict__ members, const FillArgs *__restrict__ fargs,
+             const int32_t *__restrict__ variants, const TileDev *__restrict__ tiles, int ntiles,
+             uint32_t *queue)
 {
-    extern __shared__ __align__(16) char smem[];
     __shared__ int s_tile;
-    const int tid = threadIdx.x, nthr = blockDim.x;
-    uint32_t *win = reinterpret_cast<uint32_t *>(smem + lds_win);
+    const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0)
             s_tile = (int)__hip_atomic_fetch_add(&queue[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -162,79 +127,21 @@ batch_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ 
         if (t >= ntiles)
             break;
         const TileDev tile = tiles[t];
-        const MemberDev &M = members[__builtin_amdgcn_readfirstlane(tile.member)];
-        // stage the member's learned models, zero its LDS copy
-        for (int a = 0; a < M.dims; ++a) {
-            if (M.ax[a].kind == AX_LEARNED) {
-                const uint4 *src = reinterpret_cast<const uint4 *>(M.ax[a].model);
-                uint4 *dst = reinterpret_cast<uint4 *>(smem + M.ax[a].lds_model);
-                for (int i = tid; i < M.ax[a].nseg; i += nthr)
-                    dst[i] = src[i];
-            }
+        const int m = __builtin_amdgcn_readfirstlane(tile.member);
+        const int v = __builtin_amdgcn_readfirstlane(variants[m]);
+        const FillArgs *A = fargs + m;
+        const int ks = v & 3, bacc = (v >> 2) & 3, dt = v >> 4;
+        const int col = tile.ptile, cols = members[m].ntiles;
+        const int64_t start = tile.start, end = tile.start + tile.len;
+        switch (dt) {
+        case 0: batch_tile_ks<1, double>(bacc, ks, A, start, end, col, cols); break;
+        case 1: batch_tile_ks<1, float>(bacc, ks, A, start, end, col, cols); break;
+        case 2: batch_tile_ks<2, double>(bacc, ks, A, start, end, col, cols); break;
+        case 3: batch_tile_ks<2, float>(bacc, ks, A, start, end, col, cols); break;
+        case 4: batch_tile_ks<3, double>(bacc, ks, A, start, end, col, cols); break;
+        default: batch_tile_ks<3, float>(bacc, ks, A, start, end, col, cols); break;
         }
-        const int words = M.acc == kAccPart
-                              ? M.nbuckets
-                              : (M.acc < 0 ? 0 : (M.acc == ACC_U32 ? M.win_len * M.copies : M.win_len * M.copies * 4));
-        for (int i = tid; i < words; i += nthr)
-            win[i] = 0u;
-        __syncthreads();
-        double st[kMaxStats];
-        for (int k = 0; k < kMaxStats; ++k)
-            st[k] = 0.0;
-        const bool weighted = M.w != nullptr;
-        if (M.acc == kAccPart) {
-            if (M.f32) {
-                if (weighted)
-                    batch_count_events<true, true>(M, tile.start, tile.len, smem, win, st);
-                else
-                    batch_count_events<true, false>(M, tile.start, tile.len, smem, win, st);
-            } else {
-                if (weighted)
-                    batch_count_events<false, true>(M, tile.start, tile.len, smem, win, st);
-                else
-                    batch_count_events<false, false>(M, tile.start, tile.len, smem, win, st);
-            }
-        } else if (M.f32) {
-            if (weighted)
-                batch_events<true, true>(M, tile.start, tile.len, smem, win, st);
-            else
-                batch_events<true, false>(M, tile.start, tile.len, smem, win, st);
-        } else {
-            if (weighted)
-                batch_events<false, true>(M, tile.start, tile.len, smem, win, st);
-            else
-                batch_events<false, false>(M, tile.start, tile.len, smem, win, st);
-        }
-        __syncthreads();
-        reduce_stats<kMaxStats>(st, reinterpret_cast<double *>(smem), M.stats);
-        // merge the LDS copy (kAccPart: store the tile's bucket counts)
-        if (M.acc == kAccPart) {
-            for (int j = tid; j < M.nbuckets; j += nthr)
-                M.table[(int64_t)j * M.ntiles + tile.ptile] = win[j];
-        } else if (M.acc == ACC_U32) {
-            for (int l = tid; l < M.win_len; l += nthr) {
-                uint32_t c = 0;
-                for (int r = 0; r < M.copies; ++r)
-                    c += win[l * M.copies + r];
-                if (c)
-                    gl_add_u64(&M.cnt[l], c);
-            }
-        } else if (M.acc == ACC_F64) {
-            const double *d = reinterpret_cast<const double *>(win);
-            const int n1 = M.win_len * M.copies;
-            for (int l = tid; l < M.win_len; l += nthr) {
-                double s = 0.0, s2 = 0.0;
-                for (int r = 0; r < M.copies; ++r) {
-                    s += d[l * M.copies + r];
-                    s2 += d[n1 + l * M.copies + r];
-                }
-                if (s != 0.0 || s2 != 0.0) {
-                    gl_add_f64(&M.sumw[l], s);
-                    gl_add_f64(&M.sumw2[l], s2);
-                }
-            }
-        }
-        __syncthreads();
+        __syncthreads();   // the tile's window merge is done before the next tile zeroes it
     }
     // Every workgroup has drawn past the last tile before it counts itself
     // done, so the last one can reset the queue for the next launch.
@@ -305,6 +212,8 @@ struct hist_batch_s {
     std::vector<hist_t *> hs;
     std::vector<int64_t> n;
     MemberDev *d_members = nullptr;
+    FillArgs *d_fargs = nullptr;
+    int32_t *d_variants = nullptr;
     TileDev *d_tiles = nullptr;
     uint32_t *d_queue = nullptr;
     int ntiles = 0;
@@ -334,6 +243,10 @@ static void batch_free(hist_batch_s *b)
         (void)hipStreamDestroy(b->cap_stream);
     if (b->d_members)
         (void)hipFree(b->d_members);
+    if (b->d_fargs)
+        (void)hipFree(b->d_fargs);
+    if (b->d_variants)
+        (void)hipFree(b->d_variants);
     if (b->d_tiles)
         (void)hipFree(b->d_tiles);
     if (b->d_queue)
@@ -352,7 +265,7 @@ static void batch_free(hist_batch_s *b)
 static hipError_t batch_enqueue(hist_batch_s *b, hipStream_t s)
 {
     hipLaunchKernelGGL(batch_kernel, dim3(b->blocks), dim3(b->threads), (size_t)b->lds, s,
-                       b->d_members, b->d_tiles, b->ntiles, b->d_queue, b->lds_win);
+                       b->d_members, b->d_fargs, b->d_variants, b->d_tiles, b->ntiles, b->d_queue);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || b->npart == 0)
         return e;
@@ -414,13 +327,20 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     const int avail = h0->lds_max - b->lds_win - 64;   // room for the kernel's static LDS
 
     std::vector<MemberDev> mem((size_t)k);
+    std::vector<FillArgs> fargs((size_t)k);
+    std::vector<int32_t> variants((size_t)k);
     std::vector<TileDev> tiles, ptiles;
     std::vector<int32_t> part_members;
     std::vector<ChunkDev> chunks;
     std::vector<size_t> part_off((size_t)k, 0);   // scratch offsets of kAccPart members
     size_t part_bytes = 0;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    constexpr int64_t kPartTile = 65536;          // events per count / scatter tile
+    // Tile sizes: a tile runs on one workgroup, so members whose events are
+    // latency-bound (searches, global atomics) need many tiles to spread over
+    // the CUs; LDS members get enough events per tile to amortize the zeroing
+    // and merging of their window.
+    constexpr int64_t kPartTile = 32768;          // events per count / scatter tile
+    constexpr int64_t kPartMinEvents = 4096;      // fewer events: global atomics
     int max_window_bytes = 0;
     for (int i = 0; i < k; ++i) {
         hist_s *h = hs[i];
@@ -456,11 +376,38 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
             ++pbits;
         const int64_t pnb = (h->T + ((int64_t)1 << pbits) - 1) >> pbits;
         const bool part_ok = ((int64_t)bytes << pbits) <= h0->lds_max && pnb * 4 <= avail;
+        // the member's fill arguments: every tile runs the fill body on them
+        FillArgs &fa = fargs[(size_t)i];
+        std::memset(&fa, 0, sizeof(fa));
+        for (int a = 0; a < kMaxDims; ++a) {
+            fa.ax[a] = m.ax[a];
+            fa.coords[a] = m.coords[a];
+        }
+        fa.w = d.weights;
+        fa.n = d.n;
+        fa.cnt = m.cnt;
+        fa.sumw = m.sumw;
+        fa.sumw2 = m.sumw2;
+        fa.stats = m.stats;
+        fa.lds_win = b->lds_win;
+        fa.lds_cache = -1;
+        fa.merge = MERGE_ATOMIC;
+        fa.epoch_iters = 1;
+        fa.copies = 1;
+        const int ks = kind_set(h->dims, h->ax);
+        int bacc = d.weights ? BA_F64 : BA_U32;
         if (h->T * bytes <= avail) {
             m.acc = d.weights ? ACC_F64 : ACC_U32;
             m.win_len = (int32_t)h->T;
-            max_window_bytes = std::max(max_window_bytes, (int)(h->T * bytes));
-        } else if (part_ok && d.n >= kPartTile) {
+            // interleaved copies for small histograms, within 32 KB so the
+            // per-tile zeroing and merge stay small next to the tile
+            const int64_t fit = std::min<int64_t>(avail, 32768) / (h->T * bytes);
+            m.copies = (int32_t)std::min<int64_t>(64, std::max<int64_t>(1, fit));
+            fa.win_len = m.win_len;
+            fa.copies = m.copies;
+            max_window_bytes = std::max(max_window_bytes, (int)(h->T * bytes * m.copies));
+        } else if (part_ok && d.n >= kPartMinEvents) {
+            bacc = d.weights ? BA_PCOUNT_W : BA_PCOUNT;
             m.acc = kAccPart;
             m.bshift = pbits;
             m.nbuckets = (int32_t)pnb;
@@ -477,10 +424,13 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
             const int64_t cmax = pnb + (d.n + kPartChunk - 1) / kPartChunk;
             for (int64_t t = 0; t < cmax; ++t)
                 chunks.push_back(ChunkDev{i, (int32_t)t});
+            fa.win_len = m.nbuckets;
+            fa.part_shift = m.bshift;
         } else {
             m.acc = kAccGlobal;
             m.win_len = 0;
         }
+        variants[(size_t)i] = batch_variant(h->dims, d.dtype == HIST_F32, bacc, ks);
         b->n.push_back(d.n);
         if (m.acc == kAccPart) {
             for (int32_t t = 0; t < m.ntiles; ++t) {
@@ -494,7 +444,8 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         }
         // tiles: LDS members get enough events per tile to amortize the
         // zeroing and merging of their window
-        const int64_t tile_len = m.acc >= 0 ? std::max<int64_t>(65536, 32 * (int64_t)m.win_len) : 131072;
+        const int64_t tile_len =
+            m.acc >= 0 ? std::max<int64_t>(32768, 8 * (int64_t)m.win_len * m.copies) : 16384;
         const int64_t nt = (d.n + tile_len - 1) / tile_len;
         for (int64_t t = 0; t < nt; ++t) {
             const int64_t s0 = d.n * t / nt, s1 = d.n * (t + 1) / nt;
@@ -549,6 +500,8 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
                 m.bucket_start = reinterpret_cast<uint32_t *>(q);
                 q += up((size_t)(m.nbuckets + 1) * 4);
                 m.chunk_start = reinterpret_cast<uint32_t *>(q);
+                fargs[(size_t)i].gbins = m.gbins;
+                fargs[(size_t)i].part_table = m.table;
             }
         }
         if (e == hipSuccess)
@@ -560,6 +513,14 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     }
     if (e == hipSuccess)
         e = hipMalloc(&b->d_members, sizeof(MemberDev) * (size_t)k);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_fargs, sizeof(FillArgs) * (size_t)k);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_variants, sizeof(int32_t) * (size_t)k);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_fargs, fargs.data(), sizeof(FillArgs) * (size_t)k, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_variants, variants.data(), sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMalloc(&b->d_tiles, sizeof(TileDev) * std::max<size_t>(1, tiles.size()));
     if (e == hipSuccess)
