@@ -41,6 +41,8 @@ struct MemberDev {
     uint16_t *rec_off;            // [n] in-bucket offsets in bucket order
     double *rec_w;                // [n] weights in bucket order (weighted members)
     uint32_t *table;              // [nbuckets * ntiles]
+    uint32_t *totals;             // [nbuckets] (in the batch's totals array)
+    uint32_t *cursor;             // [nbuckets]
     uint32_t *bucket_start;       // [nbuckets + 1]
     uint32_t *chunk_start;        // [nbuckets + 1]
     int64_t T;
@@ -160,7 +162,7 @@ __global__ void __launch_bounds__(1024)
 batch_part_scan_kernel(const MemberDev *__restrict__ members, const int32_t *__restrict__ part_members)
 {
     const MemberDev &M = members[part_members[blockIdx.x]];
-    part_scan(M.table, M.bucket_start, M.chunk_start, M.nbuckets, M.ntiles);
+    part_scan(M.totals, M.bucket_start, M.chunk_start, M.cursor, M.nbuckets);
 }
 
 __global__ void __launch_bounds__(kMaxThreads)
@@ -169,18 +171,18 @@ batch_part_scatter_kernel(const MemberDev *__restrict__ members, const TileDev *
     extern __shared__ __align__(16) char smem[];
     const TileDev tile = ptiles[blockIdx.x];
     const MemberDev &M = members[tile.member];
-    uint32_t *cur = reinterpret_cast<uint32_t *>(smem);
     const int64_t end = tile.start + tile.len;
     if (!M.w)
-        part_scatter<double, false>(M.gbins, nullptr, tile.start, end, M.table, M.ntiles, tile.ptile,
-                                    M.nbuckets, M.bshift, M.rec_off, M.rec_w, cur);
+        part_scatter<double, false>(M.gbins, nullptr, tile.start, end, M.table, M.cursor, M.ntiles,
+                                    tile.ptile, M.nbuckets, M.bshift, M.rec_off, M.rec_w, smem);
     else if (M.f32)
         part_scatter<float, true>(M.gbins, static_cast<const float *>(M.w), tile.start, end, M.table,
-                                  M.ntiles, tile.ptile, M.nbuckets, M.bshift, M.rec_off, M.rec_w, cur);
+                                  M.cursor, M.ntiles, tile.ptile, M.nbuckets, M.bshift, M.rec_off,
+                                  M.rec_w, smem);
     else
         part_scatter<double, true>(M.gbins, static_cast<const double *>(M.w), tile.start, end,
-                                   M.table, M.ntiles, tile.ptile, M.nbuckets, M.bshift, M.rec_off,
-                                   M.rec_w, cur);
+                                   M.table, M.cursor, M.ntiles, tile.ptile, M.nbuckets, M.bshift,
+                                   M.rec_off, M.rec_w, smem);
 }
 
 __global__ void __launch_bounds__(1024)
@@ -225,6 +227,8 @@ struct hist_batch_s {
     TileDev *d_ptiles = nullptr;
     ChunkDev *d_chunks = nullptr;
     void *d_part = nullptr;
+    uint32_t *d_totals = nullptr;                 // bucket totals of every partitioned member
+    int64_t ntotals = 0;
     int scatter_lds = 0, accum_lds = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -259,11 +263,18 @@ static void batch_free(hist_batch_s *b)
         (void)hipFree(b->d_chunks);
     if (b->d_part)
         (void)hipFree(b->d_part);
+    if (b->d_totals)
+        (void)hipFree(b->d_totals);
     delete b;
 }
 
 static hipError_t batch_enqueue(hist_batch_s *b, hipStream_t s)
 {
+    if (b->npart > 0) {
+        const hipError_t ez = launch_zero_u32(b->d_totals, b->ntotals, s);
+        if (ez != hipSuccess)
+            return ez;
+    }
     hipLaunchKernelGGL(batch_kernel, dim3(b->blocks), dim3(b->threads), (size_t)b->lds, s,
                        b->d_members, b->d_fargs, b->d_variants, b->d_tiles, b->ntiles, b->d_queue);
     hipError_t e = hipGetLastError();
@@ -333,6 +344,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     std::vector<int32_t> part_members;
     std::vector<ChunkDev> chunks;
     std::vector<size_t> part_off((size_t)k, 0);   // scratch offsets of kAccPart members
+    std::vector<int64_t> tot_off((size_t)k, 0);   // offsets in the totals array
     size_t part_bytes = 0;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     // Tile sizes: a tile runs on one workgroup, so members whose events are
@@ -413,12 +425,14 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
             m.nbuckets = (int32_t)pnb;
             m.ntiles = (int32_t)((d.n + kPartTile - 1) / kPartTile);
             max_window_bytes = std::max(max_window_bytes, (int)(pnb * 4));
-            b->scatter_lds = std::max(b->scatter_lds, (int)(pnb * 4));
+            b->scatter_lds = std::max(b->scatter_lds, part_scatter_lds((int)pnb, d.weights != nullptr));
             b->accum_lds = std::max(b->accum_lds, bytes << pbits);
             part_off[(size_t)i] = part_bytes;
             part_bytes += up((size_t)d.n * 4) + up((size_t)d.n * 2) +
                           (d.weights ? up((size_t)d.n * 8) : 0) +
-                          up((size_t)pnb * m.ntiles * 4) + 2 * up((size_t)(pnb + 1) * 4);
+                          up((size_t)pnb * m.ntiles * 4) + 3 * up((size_t)(pnb + 1) * 4);
+            tot_off[(size_t)i] = b->ntotals;
+            b->ntotals += pnb;
             part_members.push_back(i);
             // every bucket has at most ceil(records / kPartChunk) chunks
             const int64_t cmax = pnb + (d.n + kPartChunk - 1) / kPartChunk;
@@ -468,6 +482,8 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     if (b->npart > 0) {
         e = hipMalloc(&b->d_part, part_bytes);
         if (e == hipSuccess)
+            e = hipMalloc(&b->d_totals, sizeof(uint32_t) * (size_t)b->ntotals);
+        if (e == hipSuccess)
             e = hipMalloc(&b->d_part_members, sizeof(int32_t) * part_members.size());
         if (e == hipSuccess)
             e = hipMalloc(&b->d_ptiles, sizeof(TileDev) * ptiles.size());
@@ -500,8 +516,12 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
                 m.bucket_start = reinterpret_cast<uint32_t *>(q);
                 q += up((size_t)(m.nbuckets + 1) * 4);
                 m.chunk_start = reinterpret_cast<uint32_t *>(q);
+                q += up((size_t)(m.nbuckets + 1) * 4);
+                m.cursor = reinterpret_cast<uint32_t *>(q);
+                m.totals = b->d_totals + tot_off[(size_t)i];
                 fargs[(size_t)i].gbins = m.gbins;
                 fargs[(size_t)i].part_table = m.table;
+                fargs[(size_t)i].part_totals = m.totals;
             }
         }
         if (e == hipSuccess)

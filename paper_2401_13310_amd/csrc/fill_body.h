@@ -46,8 +46,12 @@ __device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A, i
     const int W = A.win_len;
     const int C = A.copies;
     if (ACC == ACC_PCOUNT) {
-        for (int j = threadIdx.x; j < W; j += blockDim.x)
-            A.part_table[(int64_t)j * cols + col] = win[j];
+        for (int j = threadIdx.x; j < W; j += blockDim.x) {
+            const uint32_t c = win[j];
+            A.part_table[(int64_t)j * cols + col] = c;
+            if (c)
+                __hip_atomic_fetch_add(&A.part_totals[j], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
     } else if (ACC == ACC_U32) {
         if (A.merge == MERGE_STAGE) {
             uint32_t *st = static_cast<uint32_t *>(A.stage) + (int64_t)col * A.stage_stride;

@@ -342,7 +342,7 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
     const int nb = (int)((h->T + ((int64_t)1 << b) - 1) >> b);
     const int G = p.blocks;
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t table_b = up((size_t)nb * G * 4), start_b = 2 * up((size_t)(nb + 1) * 4);
+    const size_t table_b = up((size_t)nb * G * 4), start_b = 4 * up((size_t)(nb + 1) * 4);
     const size_t off_b = up((size_t)mmax * 2), w_b = weighted ? up((size_t)mmax * 8) : 0;
     hist_status st = ensure_gbins(h, mmax, s);
     if (st != HIST_OK)
@@ -355,7 +355,9 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
     std::memset(&P, 0, sizeof(P));
     P.table = reinterpret_cast<uint32_t *>(base);
     P.bucket_start = reinterpret_cast<uint32_t *>(base + table_b);
-    P.chunk_start = reinterpret_cast<uint32_t *>(base + table_b + start_b / 2);
+    P.chunk_start = reinterpret_cast<uint32_t *>(base + table_b + start_b / 4);
+    P.totals = reinterpret_cast<uint32_t *>(base + table_b + 2 * (start_b / 4));
+    P.cursor = reinterpret_cast<uint32_t *>(base + table_b + 3 * (start_b / 4));
     P.rec_off = reinterpret_cast<uint16_t *>(base + table_b + start_b);
     P.rec_w = weighted ? reinterpret_cast<double *>(base + table_b + start_b + off_b) : nullptr;
     P.T = h->T;
@@ -386,11 +388,14 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
         c.copies = 1;
         c.lds_win = p.lds_base;
         c.part_table = P.table;
+        c.part_totals = P.totals;
         c.part_shift = b;
+        HIPCHK(launch_zero_u32(P.totals, nb, s), "partition totals reset");
         HIPCHK(launch_fill(h->dims, f32, ACC_PCOUNT, weighted, p.threads, g, (size_t)p.lds, c, s),
                "partition count launch");
-        HIPCHK(launch_part_scan(P, g, s), "partition scan launch");
-        HIPCHK(launch_part_scatter(f32, weighted, p.threads, g, (size_t)p.lds, c, P, s),
+        HIPCHK(launch_part_scan(P, s), "partition scan launch");
+        HIPCHK(launch_part_scatter(f32, weighted, kMaxThreads, g, (size_t)part_scatter_lds(nb, weighted),
+                                   c, P, s),
                "partition scatter launch");
         // every bucket has at most ceil(records / kPartChunk) chunks
         const int chunks_max = nb + (int)((m + kPartChunk - 1) / kPartChunk);

@@ -86,6 +86,7 @@ struct FillArgs {
     int64_t stage_stride;     // units per block: u32 words (U32/U16) or bins (F64/F32C)
     int32_t *gbins;           // TILED pass 1 / PCOUNT: global bin of every event
     uint32_t *part_table;     // PCOUNT: bucket-major counts table[bucket * gridDim.x + block]
+    uint32_t *part_totals;    // PCOUNT: events per bucket (added to with atomics)
     int32_t part_shift;       // PCOUNT: log2 of the bucket width
     int32_t pad0;
 };
@@ -108,7 +109,9 @@ struct TileArgs {
 // 2^bshift consecutive global bins) per workgroup, the counts are scanned into
 // slots, and the events are written in bucket order as in-bucket offsets.
 struct PartArgs {
-    uint32_t *table;          // [nbuckets * G] counts per (bucket, workgroup), then first slots
+    uint32_t *table;          // [nbuckets * G] counts per (bucket, workgroup)
+    uint32_t *totals;         // [nbuckets] events per bucket
+    uint32_t *cursor;         // [nbuckets] next free slot of every bucket (scatter pass)
     uint32_t *bucket_start;   // [nbuckets + 1] first slot of every bucket, then the total
     uint32_t *chunk_start;    // [nbuckets + 1] first accumulate chunk of every bucket, then the count
     uint16_t *rec_off;        // [m] bin offset within the bucket, in bucket order
@@ -125,6 +128,19 @@ struct PartArgs {
 // LDS copy and merged with coalesced atomics.
 constexpr uint32_t kPartChunk = 65536;
 
+// Scatter passes stage sub-tiles of this many events in LDS (one per thread
+// of a 1024-thread workgroup, four times), sorted by bucket.
+constexpr int kScatterTile = 4096;
+constexpr int kScatterStagedBuckets = 2048;   // more buckets: direct scatter
+
+// LDS bytes of the scatter pass for nbuckets buckets.
+__host__ __device__ inline int part_scatter_lds(int nbuckets, bool weighted)
+{
+    if (nbuckets > kScatterStagedBuckets)
+        return nbuckets * 4;
+    return 3 * nbuckets * 4 + 64 + kScatterTile * (weighted ? 12 : 4) + 8;
+}
+
 // Raises a kernel's dynamic LDS limit to the whole 160 KB (once per kernel).
 void allow_big_lds_ptr(const void *kernel);
 
@@ -138,7 +154,8 @@ hipError_t launch_tiled_bins(int dims, bool f32, bool weighted, int threads, int
                              size_t lds, const FillArgs &a, hipStream_t s);
 hipError_t launch_tile(int acc, bool f32, int threads, int blocks_x, int tiles, size_t lds,
                        const TileArgs &t, hipStream_t s);
-hipError_t launch_part_scan(const PartArgs &p, int blocks, hipStream_t s);
+hipError_t launch_part_scan(const PartArgs &p, hipStream_t s);
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_part_scatter(bool f32, bool weighted, int threads, int blocks, size_t lds,
                                const FillArgs &a, const PartArgs &p, hipStream_t s);
 hipError_t launch_part_accum(bool weighted, int threads, int blocks, size_t lds,

@@ -24,9 +24,9 @@
 
 namespace hg {
 
-__global__ void __launch_bounds__(1024) part_scan_kernel(PartArgs P, int G)
+__global__ void __launch_bounds__(1024) part_scan_kernel(PartArgs P)
 {
-    part_scan(P.table, P.bucket_start, P.chunk_start, P.nbuckets, G);
+    part_scan(P.totals, P.bucket_start, P.chunk_start, P.cursor, P.nbuckets);
 }
 
 template <typename T, bool W>
@@ -35,9 +35,8 @@ __global__ void __launch_bounds__(kMaxThreads) part_scatter_kernel(const FillArg
     extern __shared__ __align__(16) char smem[];
     const int64_t start = (int64_t)blockIdx.x * A.per_block;
     const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
-    part_scatter<T, W>(A.gbins, static_cast<const T *>(A.w), start, end, P.table, gridDim.x,
-                       blockIdx.x, P.nbuckets, P.bshift, P.rec_off, P.rec_w,
-                       reinterpret_cast<uint32_t *>(smem + P.lds_buckets));
+    part_scatter<T, W>(A.gbins, static_cast<const T *>(A.w), start, end, P.table, P.cursor,
+                       gridDim.x, blockIdx.x, P.nbuckets, P.bshift, P.rec_off, P.rec_w, smem);
 }
 
 template <bool W>
@@ -50,9 +49,26 @@ __global__ void __launch_bounds__(1024) part_accum_kernel(const FillArgs A, Part
 
 // ------------------------------------------------------------------ launchers
 
-hipError_t launch_part_scan(const PartArgs &p, int blocks, hipStream_t s)
+hipError_t launch_part_scan(const PartArgs &p, hipStream_t s)
 {
-    hipLaunchKernelGGL(part_scan_kernel, dim3(1), dim3(1024), 0, s, p, blocks);
+    hipLaunchKernelGGL(part_scan_kernel, dim3(1), dim3(1024), 0, s, p);
+    return hipGetLastError();
+}
+
+__global__ void zero_u32_grid_kernel(uint32_t *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 1024)
+        blocks = 1024;
+    hipLaunchKernelGGL(zero_u32_grid_kernel, dim3(blocks), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

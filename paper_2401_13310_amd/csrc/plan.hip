@@ -129,7 +129,14 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
 
     if (strategy == HIST_STRAT_PART) {
         p.acc = weighted ? ACC_F64 : ACC_U32;
-        int b = c.bucket_bits > 0 ? c.bucket_bits : (weighted ? 12 : 13);
+        // about one accumulate chunk of events per bucket: fewer, wider buckets
+        // would merge several chunks with atomics over wide bin ranges, more,
+        // narrower ones would scatter the events into shorter runs
+        int b = c.bucket_bits;
+        if (b <= 0) {
+            const double per_chunk = (double)h->T * (double)kPartChunk / (double)std::max<int64_t>(n, 1);
+            b = (int)std::ceil(std::log2(std::max(per_chunk, 2.0)));
+        }
         b = std::min(std::max(b, plo), phi);
         p.bucket_bits = b;
         p.win_len = 1 << b;
@@ -453,14 +460,11 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
             h->T * 16 <= h->lds_max)
             continue;
         if (strat == HIST_STRAT_PART) {
-            int lo = 0, hi = -1;
-            part_bits_range(h, weighted, p0.lds_base, lo, hi);
-            for (int b = std::max(lo, 11); b <= hi; ++b) {
-                PlanChoice c;
-                c.strategy = strat;
-                c.bucket_bits = b;
-                cands.push_back(c);
-            }
+            // the bucket width follows the fill size (see plan_from_choice),
+            // which a sample would not represent
+            PlanChoice c;
+            c.strategy = strat;
+            cands.push_back(c);
             continue;
         }
         if (strat == HIST_STRAT_LDS) {
