@@ -53,7 +53,7 @@ def parse():
     return ap.parse_args()
 
 
-FILL_SOURCES = ("fill.hip", "hist_internal.h", "device_common.h", "kernels.h")
+FILL_SOURCES = ("fill.hip", "fill_body.h", "hist_internal.h", "device_common.h", "kernels.h")
 
 
 def kernel_source_hash():
