@@ -403,6 +403,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         fa.stats = m.stats;
         fa.lds_win = b->lds_win;
         fa.lds_cache = -1;
+        fa.total_bins = (int32_t)h->T;
         fa.merge = MERGE_ATOMIC;
         fa.epoch_iters = 1;
         fa.copies = 1;

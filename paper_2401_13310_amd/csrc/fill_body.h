@@ -126,6 +126,8 @@ __device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A, i
 template <bool W>
 __device__ __forceinline__ void spill(const FillArgs &A, char *smem, int32_t g, double w)
 {
+    // keeps the global update inside the histogram whatever the bin
+    g = __builtin_elementwise_min(__builtin_elementwise_max(g, 0), A.total_bins - 1);
     if (A.lds_cache >= 0) {
         uint32_t *keys = reinterpret_cast<uint32_t *>(smem + A.lds_cache);
         const uint32_t h = ((uint32_t)g * 2654435761u) >> 16 & (uint32_t)(A.cache_slots - 1);
@@ -296,14 +298,15 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
             nin += take ? 1u : 0u;
         }
         const uint32_t l = (uint32_t)(g - A.win_lo);
-        out[j] = ACC != ACC_PCOUNT && ok && !(l < wlen);
+        const bool inw = l < wlen;
+        out[j] = ACC != ACC_PCOUNT && ok && !inw;
         any_out = any_out || out[j];
         if (ACC == ACC_PCOUNT) {
             if (ok) {
                 gb[base + (uint32_t)j * blockDim.x + threadIdx.x] = g;
                 lds_add_u32(&win[(uint32_t)g >> A.part_shift], 1u);
             }
-        } else if (ok && l < wlen) {
+        } else if (ok && inw) {
             if (ACC == ACC_U32) {
                 lds_add_u32(&win[__umul24(l, (uint32_t)A.copies) + cp], 1u);
             } else if (ACC == ACC_U16) {

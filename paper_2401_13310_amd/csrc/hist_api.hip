@@ -496,6 +496,7 @@ FillArgs hg::base_args(const hist_s *h, const void *const *coords, const void *w
     a.w = w;
     a.n = n;
     a.copies = 1;
+    a.total_bins = (int32_t)h->T;
     a.lds_cache = -1;
     a.cache_slots = 0;
     a.cnt = h->d_cnt;

@@ -141,6 +141,7 @@ __device__ __forceinline__ uint32_t key_feature(double x, const AxisDev &ax)
 // keeps the model read in bounds for any other x (whose result is discarded).
 __device__ __forceinline__ void key_seg(uint32_t f, const AxisDev &ax, int32_t &s, float &z)
 {
+#pragma clang fp contract(off)
     const uint32_t sf = f >> ax.kshift;
     s = (int32_t)(sf < (uint32_t)(ax.nseg - 1) ? sf : (uint32_t)(ax.nseg - 1));
     z = (float)(f & ax.kmask) * ax.zscale;
@@ -148,6 +149,7 @@ __device__ __forceinline__ void key_seg(uint32_t f, const AxisDev &ax, int32_t &
 
 __device__ __forceinline__ void linear_seg(double x, const AxisDev &ax, int32_t &s, float &z)
 {
+#pragma clang fp contract(off)   // t and z rounded exactly as in training
     const double t = (x - ax.x0) * ax.fscale;
     // the clamp only matters outside [e[0], e[nbins]) (and for NaN): it keeps
     // the segment index in [0, nseg) for any x
@@ -235,10 +237,11 @@ __device__ __forceinline__ void learned_intervals(const double (&x)[U], const Ax
         const float ylo = __builtin_fminf(__builtin_fmaxf(__builtin_ceilf(y), -0x1p30f), 0x1p30f);
         const float yhi =
             __builtin_fminf(__builtin_fmaxf(__builtin_floorf(y + half_hi(m[j].cw)), -0x1p30f), 0x1p30f);
-        const int32_t l = m[j].ai + (int32_t)ylo;
-        const int32_t h = m[j].ai + (int32_t)yhi;
-        const int32_t a = __builtin_elementwise_min(__builtin_elementwise_max(l, 1), ax.nbins);
-        const int32_t b = __builtin_elementwise_min(__builtin_elementwise_max(h, 1), ax.nbins);
+        // the interval may reach past [1, nbins] near the ends of the axis;
+        // the searches read the edges clamped to e[0] .. e[nbins], which for
+        // an in-range x decides like edges at -inf and +inf beyond them
+        const int32_t a = (int32_t)((uint32_t)m[j].ai + (uint32_t)(int32_t)ylo);
+        const int32_t b = (int32_t)((uint32_t)m[j].ai + (uint32_t)(int32_t)yhi);
         const bool under = x[j] < ax.xmin;
         const bool in = !under && x[j] < ax.xmax;   // false for NaN
         const int32_t flow = under ? 0 : ax.nbins + 1;
@@ -258,14 +261,22 @@ __device__ __forceinline__ void learned_intervals(const double (&x)[U], const Ax
     }
 }
 
+// Edge index clamped to the array: for an in-range x, e[0] <= x < e[nbins],
+// so a clamped read decides exactly like the virtual edges -inf below 0 and
+// +inf above nbins.
+__device__ __forceinline__ int32_t edge_index(int32_t k, int32_t nbins)
+{
+    return __builtin_elementwise_min(__builtin_elementwise_max(k, 0), nbins);
+}
+
 // Resolves U searches at once: each bin is known to lie in [lo, hi] with
 // e[lo-1] <= x < e[hi].  Intervals of two candidates (the common case after
 // the learned index) take one compare with e[lo]; wider ones halve per step.
 // The edge loads of all U events of a step are issued together so their
-// latencies overlap.  Reads only e[1 .. nbins-1].
+// latencies overlap.  Edge indices are clamped to [0, nbins].
 template <int U>
 __device__ __forceinline__ void search_lockstep(const double (&x)[U], const double *__restrict__ e,
-                                                int32_t (&lo)[U], int32_t (&hi)[U])
+                                                int32_t nbins, int32_t (&lo)[U], int32_t (&hi)[U])
 {
     bool wide = false;
 #pragma unroll
@@ -276,7 +287,7 @@ __device__ __forceinline__ void search_lockstep(const double (&x)[U], const doub
 #pragma unroll
         for (int j = 0; j < U; ++j)
             if (hi[j] > lo[j])
-                ev[j] = e[lo[j]];
+                ev[j] = e[edge_index(lo[j], nbins)];
 #pragma unroll
         for (int j = 0; j < U; ++j)
             if (hi[j] > lo[j])
@@ -292,7 +303,7 @@ __device__ __forceinline__ void search_lockstep(const double (&x)[U], const doub
 #pragma unroll
         for (int j = 0; j < U; ++j)
             if (lo[j] < hi[j])
-                ev[j] = e[((lo[j] + hi[j] + 1) >> 1) - 1];
+                ev[j] = e[edge_index(((lo[j] + hi[j] + 1) >> 1) - 1, nbins)];
         open = false;
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -305,6 +316,19 @@ __device__ __forceinline__ void search_lockstep(const double (&x)[U], const doub
                 open = open || lo[j] < hi[j];
             }
         }
+    }
+}
+
+// The halving search of one coordinate (same steps as search_lockstep).
+__device__ __forceinline__ void search_one(double x, const double *__restrict__ e, int32_t nbins,
+                                           int32_t &lo, int32_t &hi)
+{
+    while (lo < hi) {
+        const int32_t m = (lo + hi + 1) >> 1;
+        if (!(x < e[edge_index(m - 1, nbins)]))
+            lo = m;
+        else
+            hi = m - 1;
     }
 }
 
@@ -349,7 +373,7 @@ __device__ __forceinline__ void axis_bins_begin(const double (&x)[U], const Axis
     for (int j = 0; j < U; ++j) {
         ev[j] = 0.0;
         if (lo[j] < hi[j])
-            ev[j] = ax.edges[((lo[j] + hi[j] + 1) >> 1) - 1];
+            ev[j] = ax.edges[edge_index(((lo[j] + hi[j] + 1) >> 1) - 1, ax.nbins)];
     }
 }
 
@@ -370,9 +394,18 @@ __device__ __forceinline__ void axis_bins_finish(const double (&x)[U], const Axi
             hi[j] = (step && !ge) ? m - 1 : hi[j];
             open = open || lo[j] < hi[j];
         }
-        // after the learned index one step usually decides every bin
-        if (__builtin_amdgcn_ballot_w64(open))
-            search_lockstep<U>(x, ax.edges, lo, hi);
+        // after the learned index one step usually decides every bin: the
+        // rest is searched one coordinate at a time, which keeps this rare
+        // path from holding registers for all U searches at once
+        if (__builtin_amdgcn_ballot_w64(open)) {
+            if (kind == AX_LEARNED) {
+#pragma unroll
+                for (int j = 0; j < U; ++j)
+                    search_one(x[j], ax.edges, ax.nbins, lo[j], hi[j]);
+            } else {
+                search_lockstep<U>(x, ax.edges, ax.nbins, lo, hi);
+            }
+        }
     }
 #pragma unroll
     for (int j = 0; j < U; ++j)

@@ -48,8 +48,9 @@ constexpr int kTileUnroll = 4;
 __host__ __device__ constexpr int fill_unroll(int D, bool f32, bool weighted, int acc, int ks)
 {
     return ks == KS_MIXED ? (D == 2 && acc != ACC_F32C ? 2 : 1)
-                          : (acc == ACC_F32C ? 4
-                                             : (D == 1 ? ((weighted && !f32) ? 4 : 8) : (D == 2 ? 4 : 2)));
+           : acc == ACC_F32C ? 4
+           : D == 1 ? ((weighted && !f32) ? 4 : (ks == KS_LEARNED1 && !weighted ? 12 : 8))
+                    : (D == 2 ? 4 : 2);
 }
 
 // Kernel specialization for the axis kinds of a fill.
@@ -88,7 +89,7 @@ struct FillArgs {
     uint32_t *part_table;     // PCOUNT: bucket-major counts table[bucket * gridDim.x + block]
     uint32_t *part_totals;    // PCOUNT: events per bucket (added to with atomics)
     int32_t part_shift;       // PCOUNT: log2 of the bucket width
-    int32_t pad0;
+    int32_t total_bins;       // T (global bins of the histogram)
 };
 
 struct TileArgs {
