@@ -69,7 +69,23 @@ enum BatchAcc : int32_t { BA_U32 = 0, BA_F64 = 1, BA_PCOUNT = 2, BA_PCOUNT_W = 3
 
 __host__ __device__ constexpr int batch_variant(int dims, bool f32, int bacc, int ks)
 {
-    return (((dims - 1) * 2 + (f32 ? 1 : 0)) * 4 + bacc) * 4 + ks;
+    return (((dims - 1) * 2 + (f32 ? 1 : 0)) * 4 + bacc) * 8 + ks;
+}
+
+// The member's fill arguments are read through the constant address space:
+// the pointer is wave-uniform, so every field is a scalar load that the
+// compiler may hoist out of the event loop (through a generic pointer they
+// would be per-lane flat loads, re-read each iteration).
+using ConstFillArgs = __attribute__((address_space(4))) const FillArgs;
+
+// Events per thread and iteration of a tile: the tile function is called,
+// not inlined, and the registers the call convention reserves leave the
+// multi-axis bodies less room than in the single-histogram kernel.
+__host__ __device__ constexpr int batch_unroll(int D, bool f32, bool W, int ACC, int KS)
+{
+    const int u = fill_unroll(D, f32, W, ACC, KS);
+    const int cap = D == 2 && W && !f32 ? 3 : u;
+    return u < cap ? u : cap;
 }
 
 // One tile of one member: the fill body specialized for the member's variant.
@@ -77,16 +93,16 @@ __host__ __device__ constexpr int batch_variant(int dims, bool f32, int bacc, in
 // on its own; the call costs nothing next to a tile of tens of thousands of
 // events.
 template <int D, typename T, int ACC, bool W, int KS>
-__device__ __attribute__((noinline)) void batch_tile(const FillArgs *__restrict__ A, int64_t start,
-                                                     int64_t end, int col, int cols)
+__device__ __attribute__((noinline)) void batch_tile(ConstFillArgs *A, int64_t start, int64_t end,
+                                                     int col, int cols)
 {
     extern __shared__ __align__(16) char smem[];
-    fill_range<D, T, ACC, W, fill_unroll(D, sizeof(T) == 4, W, ACC, KS), KS>(*A, smem, start, end, col,
-                                                                             cols);
+    fill_range<D, T, ACC, W, batch_unroll(D, sizeof(T) == 4, W, ACC, KS), KS>(*(const FillArgs *)A, smem,
+                                                                             start, end, col, cols);
 }
 
 template <int D, typename T, int KS>
-__device__ __forceinline__ void batch_tile_acc(int bacc, const FillArgs *A, int64_t start, int64_t end,
+__device__ __forceinline__ void batch_tile_acc(int bacc, ConstFillArgs *A, int64_t start, int64_t end,
                                                int col, int cols)
 {
     switch (bacc) {
@@ -98,11 +114,13 @@ __device__ __forceinline__ void batch_tile_acc(int bacc, const FillArgs *A, int6
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void batch_tile_ks(int bacc, int ks, const FillArgs *A, int64_t start,
+__device__ __forceinline__ void batch_tile_ks(int bacc, int ks, ConstFillArgs *A, int64_t start,
                                               int64_t end, int col, int cols)
 {
     if (ks == KS_UNIFORM) {
         batch_tile_acc<D, T, KS_UNIFORM>(bacc, A, start, end, col, cols);
+    } else if (ks == KS_STAGED) {
+        batch_tile_acc<D, T, KS_STAGED>(bacc, A, start, end, col, cols);
     } else if constexpr (D == 1) {
         if (ks == KS_LEARNED1)
             batch_tile_acc<D, T, KS_LEARNED1>(bacc, A, start, end, col, cols);
@@ -131,8 +149,8 @@ batch_kernel(const MemberDev *__restrict__ members, const FillArgs *__restrict__
         const TileDev tile = tiles[t];
         const int m = __builtin_amdgcn_readfirstlane(tile.member);
         const int v = __builtin_amdgcn_readfirstlane(variants[m]);
-        const FillArgs *A = fargs + m;
-        const int ks = v & 3, bacc = (v >> 2) & 3, dt = v >> 4;
+        ConstFillArgs *A = (ConstFillArgs *)(fargs + m);
+        const int ks = v & 7, bacc = (v >> 3) & 3, dt = v >> 5;
         const int col = tile.ptile, cols = members[m].ntiles;
         const int64_t start = tile.start, end = tile.start + tile.len;
         switch (dt) {
@@ -157,11 +175,14 @@ batch_kernel(const MemberDev *__restrict__ members, const FillArgs *__restrict__
 }
 
 // Scan, scatter and accumulate passes over the kAccPart members of a batch
-// (one workgroup per member, per member tile, per member bucket).
+// (one workgroup per member, per member tile, per member bucket).  Members are
+// read through the constant address space, so their pointers are known to be
+// global (global, not flat, loads and stores).
+using ConstMember = __attribute__((address_space(4))) const MemberDev;
 __global__ void __launch_bounds__(1024)
 batch_part_scan_kernel(const MemberDev *__restrict__ members, const int32_t *__restrict__ part_members)
 {
-    const MemberDev &M = members[part_members[blockIdx.x]];
+    ConstMember &M = *(ConstMember *)(members + part_members[blockIdx.x]);
     part_scan(M.totals, M.bucket_start, M.chunk_start, M.cursor, M.nbuckets);
 }
 
@@ -170,7 +191,7 @@ batch_part_scatter_kernel(const MemberDev *__restrict__ members, const TileDev *
 {
     extern __shared__ __align__(16) char smem[];
     const TileDev tile = ptiles[blockIdx.x];
-    const MemberDev &M = members[tile.member];
+    ConstMember &M = *(ConstMember *)(members + tile.member);
     const int64_t end = tile.start + tile.len;
     if (!M.w)
         part_scatter<double, false>(M.gbins, nullptr, tile.start, end, M.table, M.cursor, M.ntiles,
@@ -190,7 +211,7 @@ batch_part_accum_kernel(const MemberDev *__restrict__ members, const ChunkDev *_
 {
     extern __shared__ __align__(16) char smem[];
     const ChunkDev ck = chunks[blockIdx.x];
-    const MemberDev &M = members[ck.member];
+    ConstMember &M = *(ConstMember *)(members + ck.member);
     if (M.w)
         part_accum_chunk<true>(ck.chunk, M.bucket_start, M.chunk_start, M.nbuckets, M.bshift, M.T,
                                M.rec_off, M.rec_w, M.cnt, M.sumw, M.sumw2, smem);
@@ -326,15 +347,13 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
 
     // LDS budget: statistics partials, then the largest set of staged models,
     // then the window of bins
-    int model_bytes = 0;
+    int axes_end = kRedBytes;
     for (int i = 0; i < k; ++i) {
-        int mb = 0;
-        for (int a = 0; a < hs[i]->dims; ++a)
-            if (hs[i]->ax[a].kind == AX_LEARNED)
-                mb += hs[i]->ax[a].nseg * (int)sizeof(ModelSeg);
-        model_bytes = std::max(model_bytes, mb);
+        AxisDev ax[kMaxDims];
+        std::memcpy(ax, hs[i]->ax, sizeof(ax));
+        axes_end = std::max(axes_end, lds_axis_layout(hs[i]->dims, ax, kRedBytes));
     }
-    b->lds_win = (kRedBytes + model_bytes + 15) & ~15;
+    b->lds_win = (axes_end + 15) & ~15;
     const int avail = h0->lds_max - b->lds_win - 64;   // room for the kernel's static LDS
 
     std::vector<MemberDev> mem((size_t)k);
@@ -359,17 +378,11 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         const hist_fill_desc &d = descs[i];
         MemberDev &m = mem[(size_t)i];
         std::memset(&m, 0, sizeof(m));
-        int off = kRedBytes;
         for (int a = 0; a < kMaxDims; ++a) {
             m.ax[a] = h->ax[a];
-            if (a < h->dims && m.ax[a].kind == AX_LEARNED) {
-                m.ax[a].lds_model = off;
-                off += m.ax[a].nseg * (int)sizeof(ModelSeg);
-            } else {
-                m.ax[a].lds_model = -1;
-            }
             m.coords[a] = a < h->dims ? d.coords[a] : nullptr;
         }
+        lds_axis_layout(h->dims, m.ax, kRedBytes);
         m.w = d.weights;
         m.n = d.n;
         m.cnt = h->d_cnt;

@@ -93,7 +93,7 @@ template <int D, typename T>
 __global__ void __launch_bounds__(kMaxThreads) findbin_kernel(const FillArgs A, int32_t *out)
 {
     extern __shared__ __align__(16) char smem[];
-    stage_models<D>(A.ax, smem);
+    stage_axes<D>(A.ax, smem);
     __syncthreads();
     const int64_t stride = (int64_t)blockDim.x * gridDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < A.n; i += stride) {
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(kMaxThreads) tiled_bins_kernel(const FillArgs 
 {
     extern __shared__ __align__(16) char smem[];
     constexpr int NS = NStats<D>::v;
-    stage_models<D>(A.ax, smem);
+    stage_axes<D>(A.ax, smem);
     __syncthreads();
     double st[NS];
 #pragma unroll
@@ -304,6 +304,8 @@ static hipError_t launch_fill_d(int acc, bool weighted, int ks, int threads, int
 {
     if (ks == KS_UNIFORM)
         return launch_fill_k<D, T, KS_UNIFORM>(acc, weighted, threads, blocks, lds, a, s);
+    if (ks == KS_STAGED)
+        return launch_fill_k<D, T, KS_STAGED>(acc, weighted, threads, blocks, lds, a, s);
     if constexpr (D == 1) {
         if (ks == KS_LEARNED1)
             return launch_fill_k<D, T, KS_LEARNED1>(acc, weighted, threads, blocks, lds, a, s);

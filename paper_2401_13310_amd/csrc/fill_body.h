@@ -229,9 +229,8 @@ __device__ __forceinline__ void load_batch(const __amdgpu_buffer_rsrc_t (&rx)[D]
 
 // Find bin, statistics and accumulation for the U loaded events of a thread
 // (events at offsets >= len are skipped).  `prefetch` issues the loads of the
-// next batch: first thing for fixed-width axes, else once the first edge
-// loads of the searches are issued, so that those, not the next batch, are
-// what the searches wait for.  Unit weights count their in-range events in
+// next batch: first thing when no search reads HBM, else once the searches are
+// done, so that they never wait for the next batch.  Unit weights count their in-range events in
 // `nin` (the w and w^2 statistics) instead of adding 1.0 twice.  Events
 // outside the LDS window are handled after the batch's LDS adds, in a branch
 // the wave skips when none of its lanes has one.
@@ -243,26 +242,45 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
                                               int32_t *gb, Prefetch &&prefetch)
 {
     constexpr int KIND = kind_of_set<KS>();
-    constexpr bool early = KIND == AX_UNIFORM;
-    if (early)
+    constexpr bool early = KIND == AX_UNIFORM || KS == KS_STAGED;
+    constexpr int ES = (KS == KS_LEARNED1 || KS == KS_BSEARCH1) ? EDGES_HBM : EDGES_ANY;
+    // Loads complete in issue order, so the next batch is requested where no
+    // later wait is for a load issued before it: first when every search
+    // reads LDS (or there is none), else after the searches, whose HBM edge
+    // loads would otherwise wait for it.  The scheduling barriers keep the
+    // loads where they are written.
+    if (early) {
         prefetch();
+        __builtin_amdgcn_sched_barrier(0);
+    }
     const uint32_t wlen = (uint32_t)A.win_len;
     double x[D][U];
-    int32_t b[D][U], lo[D][U], hi[D][U];
-    double ev[D][U];
+    int32_t b[D][U];
     bool inr[D][U];
 #pragma unroll
-    for (int a = 0; a < D; ++a) {
+    for (int a = 0; a < D; ++a)
 #pragma unroll
         for (int j = 0; j < U; ++j)
             x[a][j] = (double)cx[j][a];
-        axis_bins_begin<U, KIND>(x[a], A.ax[a], smem, lo[a], hi[a], ev[a], inr[a]);
-    }
-    if (!early)
-        prefetch();
+    if constexpr (KS == KS_STAGED) {
 #pragma unroll
-    for (int a = 0; a < D; ++a)
-        axis_bins_finish<U, KIND>(x[a], A.ax[a], lo[a], hi[a], ev[a], b[a]);
+        for (int a = 0; a < D; ++a)
+            axis_bins_staged<U, (D > 1)>(x[a], A.ax[a], smem, b[a], inr[a]);
+    } else {
+        int32_t lo[D][U], hi[D][U];
+        double ev[D][U];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            axis_bins_begin<U, KIND, ES>(x[a], A.ax[a], smem, lo[a], hi[a], ev[a], inr[a]);
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+            axis_bins_finish<U, KIND, ES>(x[a], A.ax[a], smem, lo[a], hi[a], ev[a], b[a]);
+        if (!early) {
+            __builtin_amdgcn_sched_barrier(0);
+            prefetch();
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
     float wfv[U], w2v[U], e2v[U];
     uint32_t fidx[U];
     bool fin[U];
@@ -370,7 +388,7 @@ __device__ __forceinline__ void fill_range(const FillArgs &A, char *smem, int64_
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
 
-    stage_models<D>(A.ax, smem);
+    stage_axes<D>(A.ax, smem);
     uint32_t *win = reinterpret_cast<uint32_t *>(smem + A.lds_win);
     const int words = window_words(ACC, A.win_len, A.copies);
     for (int i = tid; i < words; i += nthr)

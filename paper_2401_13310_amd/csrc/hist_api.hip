@@ -194,6 +194,7 @@ extern "C" hist_status hist_create(int dims, const hist_axis *axes, uint32_t fla
         d.nbins = ax.nbins;
         d.nbins_d = (double)ax.nbins;
         d.lds_model = -1;
+        d.lds_edges = -1;
         d.stride = stride;
         stride *= ax.nbins + 2;
         if (ax.edges) {
@@ -797,6 +798,7 @@ extern "C" hist_status hist_train_index(hist_t *h, int axis, void *stream)
         ax.nseg = nseg_f[f];
         ax.feature = f == 0 ? FEAT_KEY : FEAT_LINEAR;
         ax.lds_model = -1;
+        ax.lds_edges = -1;
         ax.x0 = e0;
         if (f == 1) {
             const double fmax = en - e0;

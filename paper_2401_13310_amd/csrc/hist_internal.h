@@ -52,8 +52,39 @@ struct AxisDev {
     int32_t keypos;         // FEAT_KEY: e[0] > 0, so every in-range x is positive
     int32_t lds_model;      // byte offset of the model staged in LDS, -1 if none
     int32_t stride;         // product of (nbins+2) of the lower axes
-    int32_t pad;
+    int32_t lds_edges;      // byte offset of the edges staged in LDS, -1 if read from HBM
 };
+
+// Variable axes with few edges keep a copy of them in LDS, so the search steps
+// read LDS instead of waiting on L2.
+constexpr int kStageEdgesMax = 4096;       // edges of one axis
+constexpr int kStageEdgesBytes = 32768;    // all staged edges of a histogram
+
+// Which of the first dims axes get their edges staged in LDS: variable axes
+// of at most kStageEdgesMax edges, in axis order while the total stays within
+// kStageEdgesBytes.  Bit a of the result is axis a.
+__host__ __device__ inline uint32_t staged_edges_mask(int dims, const AxisDev *ax)
+{
+    uint32_t mask = 0;
+    int bytes = 0;
+    for (int d = 0; d < dims; ++d) {
+        const int eb = (ax[d].nbins + 1) * (int)sizeof(double);
+        if (ax[d].kind != AX_UNIFORM && ax[d].nbins + 1 <= kStageEdgesMax && bytes + eb <= kStageEdgesBytes) {
+            mask |= 1u << d;
+            bytes += eb;
+        }
+    }
+    return mask;
+}
+
+// Edges as an LDS pointer: a distinct address space, so a staged search can
+// never be merged with the HBM one into flat loads.
+using lds_f64 = __attribute__((address_space(3))) const double;
+
+__device__ __forceinline__ lds_f64 *lds_edge_ptr(const char *smem, const AxisDev &ax)
+{
+    return (lds_f64 *)(smem + ax.lds_edges);
+}
 
 // --------------------------------------------------------------------------
 // Fixed-width axis.  The result is defined by the binary64 evaluation
@@ -229,6 +260,8 @@ __device__ __forceinline__ void learned_intervals(const double (&x)[U], const Ax
 #pragma unroll
     for (int j = 0; j < U; ++j)
         m[j] = model[s[j]];
+    // all U reads in flight before the first is used
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         const float y = model_eval(m[j], z[j]);
@@ -273,10 +306,13 @@ __device__ __forceinline__ int32_t edge_index(int32_t k, int32_t nbins)
 // e[lo-1] <= x < e[hi].  Intervals of two candidates (the common case after
 // the learned index) take one compare with e[lo]; wider ones halve per step.
 // The edge loads of all U events of a step are issued together so their
-// latencies overlap.  Edge indices are clamped to [0, nbins].
-template <int U>
-__device__ __forceinline__ void search_lockstep(const double (&x)[U], const double *__restrict__ e,
-                                                int32_t nbins, int32_t (&lo)[U], int32_t (&hi)[U])
+// latencies overlap; in the halving loop unconditionally (a finished search
+// reads a valid clamped edge and ignores it: in a plain binary search nearly
+// every search takes the same number of steps, and predicated loads would be
+// waited for one by one).  Edge indices are clamped to [0, nbins].
+template <int U, typename EP>
+__device__ __forceinline__ void search_lockstep(const double (&x)[U], EP e, int32_t nbins,
+                                                int32_t (&lo)[U], int32_t (&hi)[U])
 {
     bool wide = false;
 #pragma unroll
@@ -302,8 +338,7 @@ __device__ __forceinline__ void search_lockstep(const double (&x)[U], const doub
         double ev[U];
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            if (lo[j] < hi[j])
-                ev[j] = e[edge_index(((lo[j] + hi[j] + 1) >> 1) - 1, nbins)];
+            ev[j] = e[edge_index(((lo[j] + hi[j] + 1) >> 1) - 1, nbins)];
         open = false;
 #pragma unroll
         for (int j = 0; j < U; ++j) {
@@ -320,8 +355,8 @@ __device__ __forceinline__ void search_lockstep(const double (&x)[U], const doub
 }
 
 // The halving search of one coordinate (same steps as search_lockstep).
-__device__ __forceinline__ void search_one(double x, const double *__restrict__ e, int32_t nbins,
-                                           int32_t &lo, int32_t &hi)
+template <typename EP>
+__device__ __forceinline__ void search_one(double x, EP e, int32_t nbins, int32_t &lo, int32_t &hi)
 {
     while (lo < hi) {
         const int32_t m = (lo + hi + 1) >> 1;
@@ -341,7 +376,42 @@ __device__ __forceinline__ void search_one(double x, const double *__restrict__ 
 // the axis kind when known at compile time, or -1 to dispatch on ax.kind
 // (uniform across a wave).  `smem` is the kernel's dynamic LDS array, holding
 // the staged learned models.
-template <int U, int KIND = -1>
+// The edge loads of the first halving step of U searches, only for the
+// coordinates whose bin is not known yet (after the learned index, most):
+// random gathers cost cache bandwidth even when they hit.
+template <int U, typename EP>
+__device__ __forceinline__ void first_step_loads(EP e, int32_t nbins, const int32_t (&lo)[U],
+                                                 const int32_t (&hi)[U], double (&ev)[U])
+{
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        ev[j] = 0.0;
+        if (lo[j] < hi[j])
+            ev[j] = e[edge_index(((lo[j] + hi[j] + 1) >> 1) - 1, nbins)];
+    }
+}
+
+// The searches after the first step.  After the learned index one step usually
+// decides every bin: the rest is searched one coordinate at a time, which keeps
+// this rare path from holding registers for all U searches at once.
+template <int U, typename EP>
+__device__ __forceinline__ void finish_searches(const double (&x)[U], EP e, int32_t nbins,
+                                                bool learned, int32_t (&lo)[U], int32_t (&hi)[U])
+{
+    if (learned) {
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            search_one(x[j], e, nbins, lo[j], hi[j]);
+    } else {
+        search_lockstep<U>(x, e, nbins, lo, hi);
+    }
+}
+
+// Where a variable axis's edges are read from: HBM only (kernels whose kind
+// set excludes staged edges), or LDS whenever ax.lds_edges >= 0.
+enum EdgeSource : int32_t { EDGES_HBM = 0, EDGES_ANY = 1 };
+
+template <int U, int KIND = -1, int ES = EDGES_ANY>
 __device__ __forceinline__ void axis_bins_begin(const double (&x)[U], const AxisDev &ax,
                                                 const char *smem, int32_t (&lo)[U],
                                                 int32_t (&hi)[U], double (&ev)[U], bool (&inr)[U])
@@ -369,17 +439,15 @@ __device__ __forceinline__ void axis_bins_begin(const double (&x)[U], const Axis
             hi[j] = inr[j] ? ax.nbins : flow;
         }
     }
-#pragma unroll
-    for (int j = 0; j < U; ++j) {
-        ev[j] = 0.0;
-        if (lo[j] < hi[j])
-            ev[j] = ax.edges[edge_index(((lo[j] + hi[j] + 1) >> 1) - 1, ax.nbins)];
-    }
+    if (ES == EDGES_ANY && ax.lds_edges >= 0)
+        first_step_loads<U>(lds_edge_ptr(smem, ax), ax.nbins, lo, hi, ev);
+    else
+        first_step_loads<U>(ax.edges, ax.nbins, lo, hi, ev);
 }
 
-template <int U, int KIND = -1>
+template <int U, int KIND = -1, int ES = EDGES_ANY>
 __device__ __forceinline__ void axis_bins_finish(const double (&x)[U], const AxisDev &ax,
-                                                 int32_t (&lo)[U], int32_t (&hi)[U],
+                                                 const char *smem, int32_t (&lo)[U], int32_t (&hi)[U],
                                                  const double (&ev)[U], int32_t (&b)[U])
 {
     const int kind = KIND >= 0 ? KIND : ax.kind;
@@ -394,17 +462,11 @@ __device__ __forceinline__ void axis_bins_finish(const double (&x)[U], const Axi
             hi[j] = (step && !ge) ? m - 1 : hi[j];
             open = open || lo[j] < hi[j];
         }
-        // after the learned index one step usually decides every bin: the
-        // rest is searched one coordinate at a time, which keeps this rare
-        // path from holding registers for all U searches at once
         if (__builtin_amdgcn_ballot_w64(open)) {
-            if (kind == AX_LEARNED) {
-#pragma unroll
-                for (int j = 0; j < U; ++j)
-                    search_one(x[j], ax.edges, ax.nbins, lo[j], hi[j]);
-            } else {
-                search_lockstep<U>(x, ax.edges, ax.nbins, lo, hi);
-            }
+            if (ES == EDGES_ANY && ax.lds_edges >= 0)
+                finish_searches<U>(x, lds_edge_ptr(smem, ax), ax.nbins, kind == AX_LEARNED, lo, hi);
+            else
+                finish_searches<U>(x, ax.edges, ax.nbins, kind == AX_LEARNED, lo, hi);
         }
     }
 #pragma unroll
@@ -420,12 +482,46 @@ __device__ __forceinline__ void axis_bins(const double (&x)[U], const AxisDev &a
     double ev[U];
     bool inr[U];
     axis_bins_begin<U, KIND>(x, ax, smem, lo, hi, ev, inr);
-    axis_bins_finish<U, KIND>(x, ax, lo, hi, ev, b);
+    axis_bins_finish<U, KIND>(x, ax, smem, lo, hi, ev, b);
 }
 
-// Copies the learned models of the first D axes to their LDS offsets.
+// Bins of U coordinates on an axis of any kind whose edges (if any) are staged
+// in LDS: every step reads LDS, so nothing here waits on the event loads in
+// flight, and one axis is finished before the next is begun (only one axis's
+// search state is live at a time).  MAY_UNIFORM false: the axis is known to be
+// variable.
+template <int U, bool MAY_UNIFORM>
+__device__ __forceinline__ void axis_bins_staged(const double (&x)[U], const AxisDev &ax,
+                                                 const char *smem, int32_t (&b)[U], bool (&inr)[U])
+{
+    if (MAY_UNIFORM && ax.kind == AX_UNIFORM) {
+        bins_uniform<U>(x, ax, b, inr);
+        return;
+    }
+    int32_t lo[U], hi[U];
+    if (ax.kind == AX_LEARNED) {
+        learned_intervals<U>(x, ax, reinterpret_cast<const ModelSeg *>(smem + ax.lds_model), lo, hi,
+                             inr);
+    } else {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const bool under = x[j] < ax.xmin;
+            inr[j] = !under && x[j] < ax.xmax;
+            const int32_t flow = under ? 0 : ax.nbins + 1;
+            lo[j] = inr[j] ? 1 : flow;
+            hi[j] = inr[j] ? ax.nbins : flow;
+        }
+    }
+    search_lockstep<U>(x, lds_edge_ptr(smem, ax), ax.nbins, lo, hi);
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        b[j] = lo[j];
+}
+
+// Copies the learned models and the staged edges of the first D axes to
+// their LDS offsets.
 template <int D>
-__device__ __forceinline__ void stage_models(const AxisDev (&ax)[kMaxDims], char *smem)
+__device__ __forceinline__ void stage_axes(const AxisDev (&ax)[kMaxDims], char *smem)
 {
 #pragma unroll
     for (int a = 0; a < D; ++a) {
@@ -436,11 +532,19 @@ __device__ __forceinline__ void stage_models(const AxisDev (&ax)[kMaxDims], char
             for (int i = threadIdx.x; i < nd; i += blockDim.x)
                 dst[i] = src[i];
         }
+        if (ax[a].kind != AX_UNIFORM && ax[a].lds_edges >= 0) {
+            double *dst = reinterpret_cast<double *>(smem + ax[a].lds_edges);
+            for (int i = threadIdx.x; i <= ax[a].nbins; i += blockDim.x)
+                dst[i] = ax[a].edges[i];
+        }
     }
 }
 
 // Kernel specializations by the kinds of the axes.
-enum KindSet : int32_t { KS_UNIFORM = 0, KS_LEARNED1 = 1, KS_BSEARCH1 = 2, KS_MIXED = 3 };
+// KS_STAGED: some axis is variable and every variable axis has its edges in
+// LDS (any dims, kinds dispatched at run time).
+enum KindSet : int32_t { KS_UNIFORM = 0, KS_LEARNED1 = 1, KS_BSEARCH1 = 2, KS_MIXED = 3, KS_STAGED = 4 };
+constexpr int kKindSets = 5;
 
 template <int KS>
 __host__ __device__ constexpr int kind_of_set()

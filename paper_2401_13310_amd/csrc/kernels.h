@@ -44,13 +44,22 @@ constexpr int kTileUnroll = 4;
 // Events each thread loads per loop iteration of the fill kernel.
 // Sized so the double-buffered batch fits the 128 VGPRs a 1024-thread
 // workgroup allows without spilling; kernels that dispatch on the axis kinds
-// at run time (KS_MIXED) carry every kind's code and get fewer events.
+// at run time (KS_MIXED, KS_STAGED) carry every kind's code and get fewer
+// events.
 __host__ __device__ constexpr int fill_unroll(int D, bool f32, bool weighted, int acc, int ks)
 {
-    return ks == KS_MIXED ? (D == 2 && acc != ACC_F32C ? 2 : 1)
-           : acc == ACC_F32C ? 4
-           : D == 1 ? ((weighted && !f32) ? 4 : (ks == KS_LEARNED1 && !weighted ? 12 : 8))
-                    : (D == 2 ? 4 : 2);
+    const bool w64 = weighted && !f32;
+    if (ks == KS_MIXED)
+        return (D == 2 && acc != ACC_F32C) ? 2 : 1;
+    if (ks == KS_STAGED)
+        return acc == ACC_F32C ? 2 : (D == 1 ? (weighted ? 4 : 6) : (D == 2 ? (weighted ? 3 : 4) : 2));
+    if (acc == ACC_F32C)
+        return 4;
+    if (D == 1)
+        return w64 ? 4 : 8;
+    if (D == 2)
+        return 4;
+    return 2;
 }
 
 // Kernel specialization for the axis kinds of a fill.
@@ -61,6 +70,12 @@ __host__ __device__ inline int kind_set(int dims, const AxisDev *ax)
         all_uniform = all_uniform && ax[d].kind == AX_UNIFORM;
     if (all_uniform)
         return KS_UNIFORM;
+    const uint32_t staged = staged_edges_mask(dims, ax);
+    bool all_staged = true;
+    for (int d = 0; d < dims; ++d)
+        all_staged = all_staged && (ax[d].kind == AX_UNIFORM || (staged & (1u << d)));
+    if (all_staged)
+        return KS_STAGED;
     if (dims == 1)
         return ax[0].kind == AX_LEARNED ? KS_LEARNED1 : KS_BSEARCH1;
     return KS_MIXED;

@@ -92,6 +92,9 @@ FillArgs base_args(const hist_s *h, const void *const *coords, const void *w, in
 // Places the learned models of the axes in LDS after the statistics area;
 // returns the first free LDS byte.
 int apply_model_offsets(const hist_s *h, FillArgs &a);
+// LDS offsets of the learned models and staged edges of dims axes from byte
+// `off` on; returns the first free byte (16-aligned).
+int lds_axis_layout(int dims, AxisDev *ax, int off);
 Plan make_plan(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted);
 Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted,
                       const PlanChoice &c);

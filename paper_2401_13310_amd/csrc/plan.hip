@@ -25,19 +25,30 @@ int unroll_of(const hist_s *h, bool f32, bool weighted, int acc)
     return fill_unroll(h->dims, f32, weighted, acc, kind_set(h->dims, h->ax));
 }
 
-int apply_model_offsets(const hist_s *h, FillArgs &a)
+int lds_axis_layout(int dims, AxisDev *ax, int off)
 {
-    int off = kRedBytes;
-    for (int d = 0; d < h->dims; ++d) {
-        if (a.ax[d].kind == AX_LEARNED) {
-            a.ax[d].lds_model = off;
-            off += a.ax[d].nseg * (int)sizeof(ModelSeg);
+    const uint32_t staged = staged_edges_mask(dims, ax);
+    for (int d = 0; d < dims; ++d) {
+        if (ax[d].kind == AX_LEARNED) {
+            ax[d].lds_model = off;
+            off += ax[d].nseg * (int)sizeof(ModelSeg);
             off = (off + 15) & ~15;
         } else {
-            a.ax[d].lds_model = -1;
+            ax[d].lds_model = -1;
+        }
+        if (staged & (1u << d)) {
+            ax[d].lds_edges = off;
+            off = (off + (ax[d].nbins + 1) * (int)sizeof(double) + 15) & ~15;
+        } else {
+            ax[d].lds_edges = -1;
         }
     }
     return off;
+}
+
+int apply_model_offsets(const hist_s *h, FillArgs &a)
+{
+    return lds_axis_layout(h->dims, a.ax, kRedBytes);
 }
 
 size_t stage_bytes_for(const Plan &p)
