@@ -83,7 +83,8 @@ using ConstFillArgs = __attribute__((address_space(4))) const FillArgs;
 // multi-axis bodies less room than in the single-histogram kernel.
 __host__ __device__ constexpr int batch_unroll(int D, bool f32, bool W, int ACC, int KS)
 {
-    const int u = fill_unroll(D, f32, W, ACC, KS);
+    // (a count tile runs at the batch kernel's occupancy, like a window tile)
+    const int u = fill_unroll(D, f32, W, ACC == ACC_PCOUNT ? (W ? ACC_F64 : ACC_U32) : ACC, KS);
     const int cap = D == 2 && W && !f32 ? 3 : u;
     return u < cap ? u : cap;
 }

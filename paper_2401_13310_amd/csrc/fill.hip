@@ -34,6 +34,17 @@ __global__ void __launch_bounds__(kMaxThreads) fill_kernel(const FillArgs A)
     fill_range<D, T, ACC, W, U, KS>(A, smem, start, end, blockIdx.x, gridDim.x);
 }
 
+// The same body at two workgroups per CU (the partition count pass of
+// fixed-width axes).
+template <int D, typename T, int ACC, bool W, int U, int KS>
+__global__ void __launch_bounds__(kMaxThreads, kCountWavesPerSimd) fill_kernel_x2(const FillArgs A)
+{
+    extern __shared__ __align__(16) char smem[];
+    const int64_t start = (int64_t)blockIdx.x * A.per_block;
+    const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
+    fill_range<D, T, ACC, W, U, KS>(A, smem, start, end, blockIdx.x, gridDim.x);
+}
+
 // Sums the staging slots of `nblocks` fill workgroups into the histogram.
 // blockIdx.y selects a group of slots; groups add with coalesced atomics.
 template <int ACC>
@@ -269,9 +280,16 @@ template <int D, typename T, int ACC, bool W, int KS>
 static hipError_t launch_fill_t(int threads, int blocks, size_t lds, const FillArgs &a,
                                 hipStream_t s)
 {
-    auto k = fill_kernel<D, T, ACC, W, fill_unroll(D, sizeof(T) == 4, W, ACC, KS), KS>;
-    allow_big_lds(k);
-    hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a);
+    constexpr int U = fill_unroll(D, sizeof(T) == 4, W, ACC, KS);
+    if constexpr (ACC == ACC_PCOUNT && KS == KS_UNIFORM) {
+        auto k = fill_kernel_x2<D, T, ACC, W, U, KS>;
+        allow_big_lds(k);
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a);
+    } else {
+        auto k = fill_kernel<D, T, ACC, W, U, KS>;
+        allow_big_lds(k);
+        hipLaunchKernelGGL(k, dim3(blocks), dim3(threads), lds, s, a);
+    }
     return hipGetLastError();
 }
 

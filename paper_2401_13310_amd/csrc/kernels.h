@@ -46,9 +46,17 @@ constexpr int kTileUnroll = 4;
 // workgroup allows without spilling; kernels that dispatch on the axis kinds
 // at run time (KS_MIXED, KS_STAGED) carry every kind's code and get fewer
 // events.
+// The partition count pass keeps only bucket counters in LDS, so two
+// 1024-thread workgroups share a CU when a thread stays within 64 VGPRs
+// (8 waves per SIMD): fewer events per thread, twice the waves to hide
+// latency with.
+constexpr int kCountWavesPerSimd = 8;
+
 __host__ __device__ constexpr int fill_unroll(int D, bool f32, bool weighted, int acc, int ks)
 {
     const bool w64 = weighted && !f32;
+    if (acc == ACC_PCOUNT && ks == KS_UNIFORM)
+        return D == 1 ? (w64 ? 2 : 4) : (D == 2 ? (w64 ? 1 : 2) : 1);
     if (ks == KS_MIXED)
         return (D == 2 && acc != ACC_F32C) ? 2 : 1;
     if (ks == KS_STAGED)
