@@ -154,7 +154,10 @@ constexpr uint32_t kPartChunk = 65536;
 
 // Scatter passes stage sub-tiles of this many events in LDS (one per thread
 // of a 1024-thread workgroup, four times), sorted by bucket.
-constexpr int kScatterTile = 4096;
+// Events a scatter sub-tile sorts in LDS: longer sub-tiles give longer runs
+// per bucket in the records (fewer partly written lines), bounded by the LDS
+// that staging a weighted record takes.
+__host__ __device__ constexpr int scatter_tile(bool weighted) { return weighted ? 4096 : 8192; }
 constexpr int kScatterStagedBuckets = 2048;   // more buckets: direct scatter
 
 // LDS bytes of the scatter pass for nbuckets buckets.
@@ -162,7 +165,7 @@ __host__ __device__ inline int part_scatter_lds(int nbuckets, bool weighted)
 {
     if (nbuckets > kScatterStagedBuckets)
         return nbuckets * 4;
-    return 3 * nbuckets * 4 + 64 + kScatterTile * (weighted ? 12 : 4) + 8;
+    return 3 * nbuckets * 4 + 64 + scatter_tile(weighted) * (weighted ? 12 : 4) + 8;
 }
 
 // Raises a kernel's dynamic LDS limit to the whole 160 KB (once per kernel).

@@ -135,7 +135,7 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *red, u
 // slots in every bucket with one atomic add on the bucket's cursor (ranges
 // thus take their places in a bucket in any order), then each event, in bucket
 // order, gets its bin's offset in the bucket (and its weight).  With few
-// buckets, sub-tiles of kScatterTile events are first sorted by bucket in LDS
+// buckets, sub-tiles of scatter_tile(W) events are first sorted by bucket in LDS
 // (a counting sort), so the writes to each bucket leave as contiguous runs.
 template <typename T, bool W>
 __device__ __forceinline__ void part_scatter(const int32_t *__restrict__ gbins, const T *__restrict__ w,
@@ -167,24 +167,25 @@ __device__ __forceinline__ void part_scatter(const int32_t *__restrict__ gbins, 
     uint32_t *off = hist + nbuckets;
     uint32_t *red = off + nbuckets;             // 16 words
     uint32_t *sg = red + 16;                    // staged bins
-    double *sw = reinterpret_cast<double *>(smem + ((3 * nbuckets * 4 + 64 + kScatterTile * 4 + 7) & ~7));
-    constexpr int K = kScatterTile / kMaxThreads;   // events per thread and sub-tile (nthr = 1024)
-    for (int64_t t0 = begin; t0 < end; t0 += kScatterTile) {
-        const int cnt = (int)(end - t0 < kScatterTile ? end - t0 : kScatterTile);
+    constexpr int kTile = scatter_tile(W);
+    double *sw = reinterpret_cast<double *>(smem + ((3 * nbuckets * 4 + 64 + kTile * 4 + 7) & ~7));
+    constexpr int K = kTile / kMaxThreads;      // events per thread and sub-tile (nthr = 1024)
+    for (int64_t t0 = begin; t0 < end; t0 += kTile) {
+        const int cnt = (int)(end - t0 < kTile ? end - t0 : kTile);
         for (int j = tid; j < nbuckets; j += nthr)
             hist[j] = 0u;
-        __syncthreads();
         uint32_t g[K], rank[K];
         double wv[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int e = tid + k * nthr;
             if (e < cnt) {
-                g[k] = (uint32_t)gbins[t0 + e];
+                g[k] = (uint32_t)__builtin_nontemporal_load(gbins + t0 + e);
                 if (W)
                     wv[k] = (double)__builtin_nontemporal_load(w + t0 + e);
             }
         }
+        __syncthreads();
 #pragma unroll
         for (int k = 0; k < K; ++k)
             if (tid + k * nthr < cnt)

@@ -29,8 +29,10 @@ __global__ void __launch_bounds__(1024) part_scan_kernel(PartArgs P)
     part_scan(P.totals, P.bucket_start, P.chunk_start, P.cursor, P.nbuckets);
 }
 
+// Unit weights: 64 VGPRs, so two workgroups share a CU and one's barriers
+// overlap the other's loads and stores.
 template <typename T, bool W>
-__global__ void __launch_bounds__(kMaxThreads) part_scatter_kernel(const FillArgs A, PartArgs P)
+__global__ void __launch_bounds__(kMaxThreads, W ? 4 : 8) part_scatter_kernel(const FillArgs A, PartArgs P)
 {
     extern __shared__ __align__(16) char smem[];
     const int64_t start = (int64_t)blockIdx.x * A.per_block;
