@@ -6,6 +6,8 @@
 #include "device_common.h"
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace hg {
 
 // 32-bit words of the LDS window arrays.
@@ -228,13 +230,13 @@ __device__ __forceinline__ void load_batch(const __amdgpu_buffer_rsrc_t (&rx)[D]
 }
 
 // Find bin, statistics and accumulation for the U loaded events of a thread
-// (events at offsets >= len are skipped).  `prefetch` issues the loads of the
+// (events at offsets >= len are skipped; FULL: none is).  `prefetch` issues the loads of the
 // next batch: first thing when no search reads HBM, else once the searches are
 // done, so that they never wait for the next batch.  Unit weights count their in-range events in
 // `nin` (the w and w^2 statistics) instead of adding 1.0 twice.  Events
 // outside the LDS window are handled after the batch's LDS adds, in a branch
 // the wave skips when none of its lanes has one.
-template <int D, typename T, int ACC, bool W, int U, int KS, typename Prefetch>
+template <int D, typename T, int ACC, bool W, int U, int KS, bool FULL, typename Prefetch>
 __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uint32_t *win,
                                               const T (&cx)[U][D], const T (&cw)[U],
                                               uint32_t base, uint32_t len, int cp,
@@ -290,7 +292,7 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
 #pragma unroll
     for (int j = 0; j < U; ++j) {
         fin[j] = false;
-        const bool ok = base + (uint32_t)j * blockDim.x + threadIdx.x < len;
+        const bool ok = FULL || base + (uint32_t)j * blockDim.x + threadIdx.x < len;
         int32_t g = 0;
         bool inside = true;
         double xe[D];
@@ -422,11 +424,13 @@ __device__ __forceinline__ void fill_range(const FillArgs &A, char *smem, int64_
     T cx[U][D], cw[U];
     if (len > 0)
         load_batch<D, T, W, U>(xb, wb, 0, cx, cw);
-    for (uint32_t base = 0; base < len; base += step) {
+    // full batches first, with no per-event range check, then the block's
+    // partial last batch (if any) in a loop of its own
+    auto iteration = [&](uint32_t base, auto full) {
         T nx[U][D], nw[U];
-        process_batch<D, T, ACC, W, U, KS>(A, smem, win, cx, cw, base, len, cp, st, nin, gb, [&] {
-            load_batch<D, T, W, U>(xb, wb, base + step, nx, nw);
-        });
+        process_batch<D, T, ACC, W, U, KS, decltype(full)::value>(
+            A, smem, win, cx, cw, base, len, cp, st, nin, gb,
+            [&] { load_batch<D, T, W, U>(xb, wb, base + step, nx, nw); });
         if (ACC == ACC_U16 && ++it == A.epoch_iters) {
             it = 0;
             __syncthreads();
@@ -440,7 +444,12 @@ __device__ __forceinline__ void fill_range(const FillArgs &A, char *smem, int64_
                 cx[j][a] = nx[j][a];
             cw[j] = nw[j];
         }
-    }
+    };
+    uint32_t base = 0;
+    for (; base + step <= len; base += step)
+        iteration(base, std::true_type{});
+    for (; base < len; base += step)
+        iteration(base, std::false_type{});
     if (!W) {
         st[0] = (double)nin;
         st[1] = (double)nin;
