@@ -155,6 +155,65 @@ def test_findbin_3d_and_float32(hg):
     assert_bins_equal(got32, oracle.findbin(wl["axes"], [c.astype(np.float64) for c in x32]))
 
 
+# ---------------------------------------------- edges staged in LDS (fills) --
+# Variable axes of at most 4096 edges (32 KB of edges per histogram) are
+# copied to LDS and searched there; fills whose variable axes are all staged
+# run a kernel that reads edges from LDS only.  These cases pin the staged
+# searches (learned and binary) against the oracle, at the size limit and
+# past it, and a histogram whose edge budget stages only some of its axes.
+
+def _staged_sets():
+    rng = np.random.default_rng(11)
+    sets = {k: v for k, v in _edge_sets().items() if v.size <= 4096}
+    sets["at_limit_4096_edges"] = synth._sorted_edges(rng, 4095, -3.0, 3.0)
+    sets["past_limit_4097_edges"] = synth._sorted_edges(rng, 4096, -3.0, 3.0)
+    return sets
+
+
+@pytest.mark.parametrize("learned", [False, True])
+@pytest.mark.parametrize("name", list(_staged_sets()))
+def test_fill_staged_edges_1d(hg, name, learned):
+    e = _staged_sets()[name]
+    ax = [{"nbins": e.size - 1, "edges": e}]
+    rng = np.random.default_rng(e.size)
+    span = e[-1] - e[0]
+    n = 300_001
+    x = (rng.uniform(e[0] - 0.05 * span, e[-1] + 0.05 * span, n) if np.isfinite(span)
+         else rng.normal(0, 1e3, n))
+    x[:1000] = rng.choice(e, 1000)   # exact edges: the lower edge belongs to the bin
+    # coordinates near 1e300 overflow the x^2 statistic (inf on both sides,
+    # or NaN where the oracle's sum order meets inf - inf): bins only there
+    finite = bool(np.all(np.abs(x) < 1e150))
+    fill_and_compare(hg, ax, [x], None, learned=learned, check_sums=finite)
+    w = rng.uniform(0.0, 2.0, n)
+    h, got, want = fill_and_compare(hg, ax, [x], w, learned=learned, check_sums=finite)
+    if not finite:
+        assert_sums_close(got[0], want[0], what="sumw")
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_fill_staged_edges_3d(hg, learned):
+    rng = np.random.default_rng(12)
+    axes = [{"nbins": 30, "edges": synth._sorted_edges(rng, 30, -4.0, 4.0)},
+            {"nbins": 17, "xmin": -3.0, "xmax": 3.0},
+            {"nbins": 45, "edges": synth._sorted_edges(rng, 45, -4.0, 4.0)}]
+    n = 400_003
+    coords = [rng.normal(0, 1, n) for _ in range(3)]
+    fill_and_compare(hg, axes, coords, None, learned=learned)
+    fill_and_compare(hg, axes, coords, rng.uniform(0.0, 2.0, n), learned=learned)
+
+
+def test_fill_edges_partly_staged(hg):
+    # 2 x 2101 edges: the first axis fits the 32 KB budget, the second is
+    # searched in HBM, so the fill mixes both kinds of search
+    rng = np.random.default_rng(13)
+    axes = [{"nbins": 2100, "edges": synth._sorted_edges(rng, 2100, -4.0, 4.0)} for _ in range(2)]
+    n = 200_001
+    coords = [rng.normal(0, 1, n) for _ in range(2)]
+    for learned in (False, True):
+        fill_and_compare(hg, axes, coords, None, learned=learned, strategy=hg.HIST_STRAT_GLOBAL)
+
+
 # ---------------------------------------------------------------------- fill --
 
 def test_fill_plain_1d_full_size(hg):
