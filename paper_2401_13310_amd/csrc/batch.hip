@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(1024)
 batch_part_scan_kernel(const MemberDev *__restrict__ members, const int32_t *__restrict__ part_members)
 {
     ConstMember &M = *(ConstMember *)(members + part_members[blockIdx.x]);
-    part_scan(M.totals, M.bucket_start, M.chunk_start, M.cursor, M.nbuckets);
+    part_scan(M.totals, M.bucket_start, M.chunk_start, M.cursor, M.nbuckets, kBatchPartChunk);
 }
 
 __global__ void __launch_bounds__(kMaxThreads)
@@ -215,10 +215,10 @@ batch_part_accum_kernel(const MemberDev *__restrict__ members, const ChunkDev *_
     ConstMember &M = *(ConstMember *)(members + ck.member);
     if (M.w)
         part_accum_chunk<true>(ck.chunk, M.bucket_start, M.chunk_start, M.nbuckets, M.bshift, M.T,
-                               M.rec_off, M.rec_w, M.cnt, M.sumw, M.sumw2, smem);
+                               M.rec_off, M.rec_w, M.cnt, M.sumw, M.sumw2, smem, kBatchPartChunk);
     else
         part_accum_chunk<false>(ck.chunk, M.bucket_start, M.chunk_start, M.nbuckets, M.bshift, M.T,
-                                M.rec_off, M.rec_w, M.cnt, M.sumw, M.sumw2, smem);
+                                M.rec_off, M.rec_w, M.cnt, M.sumw, M.sumw2, smem, kBatchPartChunk);
 }
 
 __global__ void zero_u32_kernel(uint32_t *p, int n)
@@ -449,8 +449,8 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
             tot_off[(size_t)i] = b->ntotals;
             b->ntotals += pnb;
             part_members.push_back(i);
-            // every bucket has at most ceil(records / kPartChunk) chunks
-            const int64_t cmax = pnb + (d.n + kPartChunk - 1) / kPartChunk;
+            // every bucket has at most ceil(records / kBatchPartChunk) chunks
+            const int64_t cmax = pnb + (d.n + kBatchPartChunk - 1) / kBatchPartChunk;
             for (int64_t t = 0; t < cmax; ++t)
                 chunks.push_back(ChunkDev{i, (int32_t)t});
             fa.win_len = m.nbuckets;

@@ -151,9 +151,10 @@ struct PartArgs {
 // with more records is split into chunks of this many, each added in its own
 // LDS copy and merged with coalesced atomics.
 constexpr uint32_t kPartChunk = 65536;
+// A batch's members share the accumulate launch with every other member, so
+// shorter chunks balance it better (its buckets do not depend on the chunk).
+constexpr uint32_t kBatchPartChunk = 32768;
 
-// Scatter passes stage sub-tiles of this many events in LDS (one per thread
-// of a 1024-thread workgroup, four times), sorted by bucket.
 // Events a scatter sub-tile sorts in LDS: longer sub-tiles give longer runs
 // per bucket in the records (fewer partly written lines), bounded by the LDS
 // that staging a weighted record takes.

@@ -71,10 +71,11 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(int64_t total, Get &&ge
 // Scan pass (one workgroup of 1024 threads) over the events per bucket:
 // bucket j holds slots [bucket_start[j], bucket_start[j+1]), its scatter
 // cursor starts at bucket_start[j], and its records are cut into chunks of at
-// most kPartChunk, numbered from chunk_start[j] (chunk count in
+// most `chunk`, numbered from chunk_start[j] (chunk count in
 // chunk_start[nbuckets]).
 __device__ __forceinline__ void part_scan(const uint32_t *totals, uint32_t *bucket_start,
-                                          uint32_t *chunk_start, uint32_t *cursor, int nbuckets)
+                                          uint32_t *chunk_start, uint32_t *cursor, int nbuckets,
+                                          uint32_t chunk)
 {
     const uint32_t total = block_exclusive_scan(
         nbuckets, [&](int64_t j) { return totals[j]; },
@@ -89,7 +90,7 @@ __device__ __forceinline__ void part_scan(const uint32_t *totals, uint32_t *buck
         nbuckets,
         [&](int64_t j) {
             const uint32_t r = bucket_start[j + 1] - bucket_start[j];
-            return (r + kPartChunk - 1) / kPartChunk;
+            return (r + chunk - 1) / chunk;
         },
         [&](int64_t j, uint32_t v) { chunk_start[j] = v; });
     if (threadIdx.x == 0)
@@ -242,7 +243,8 @@ __device__ __forceinline__ void part_accum_chunk(uint32_t t, const uint32_t *buc
                                                  int bshift, int64_t T,
                                                  const uint16_t *__restrict__ rec_off,
                                                  const double *__restrict__ rec_w, uint64_t *cnt,
-                                                 double *sumw, double *sumw2, char *smem)
+                                                 double *sumw, double *sumw2, char *smem,
+                                                 uint32_t chunk)
 {
     if (t >= chunk_start[nbuckets])
         return;
@@ -260,8 +262,8 @@ __device__ __forceinline__ void part_accum_chunk(uint32_t t, const uint32_t *buc
     const uint32_t c = t - chunk_start[j];
     const bool shared = chunk_start[j + 1] - chunk_start[j] > 1;
     const uint32_t b0 = bucket_start[j], b1 = bucket_start[j + 1];
-    const uint32_t r0 = b0 + c * kPartChunk;
-    const uint32_t r1 = r0 + kPartChunk < b1 ? r0 + kPartChunk : b1;
+    const uint32_t r0 = b0 + c * chunk;
+    const uint32_t r1 = r0 + chunk < b1 ? r0 + chunk : b1;
     const int64_t g0 = (int64_t)j << bshift;
     const int64_t bw = (int64_t)1 << bshift;
     const int len = (int)((T - g0) < bw ? (T - g0) : bw);

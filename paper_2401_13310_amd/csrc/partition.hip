@@ -26,7 +26,7 @@ namespace hg {
 
 __global__ void __launch_bounds__(1024) part_scan_kernel(PartArgs P)
 {
-    part_scan(P.totals, P.bucket_start, P.chunk_start, P.cursor, P.nbuckets);
+    part_scan(P.totals, P.bucket_start, P.chunk_start, P.cursor, P.nbuckets, kPartChunk);
 }
 
 // Unit weights: 64 VGPRs, so two workgroups share a CU and one's barriers
@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(1024) part_accum_kernel(const FillArgs A, Part
 {
     extern __shared__ __align__(16) char smem[];
     part_accum_chunk<W>(blockIdx.x, P.bucket_start, P.chunk_start, P.nbuckets, P.bshift, P.T,
-                        P.rec_off, P.rec_w, A.cnt, A.sumw, A.sumw2, smem);
+                        P.rec_off, P.rec_w, A.cnt, A.sumw, A.sumw2, smem, kPartChunk);
 }
 
 // ------------------------------------------------------------------ launchers
