@@ -203,7 +203,12 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
                 copies = c.copies;
             } else {
                 const int64_t fit = avail / std::max<int64_t>(1, len * acc_bytes(acc));
-                copies = (int)std::min<int64_t>(64, std::max<int64_t>(1, fit));
+                // every copy is zeroed and merged once per workgroup: keep at
+                // least about 4 events per bin and copy (at two workgroups
+                // per CU), or a small fill spends its time on the copies
+                const int64_t per_wg = n / std::max<int64_t>(1, (int64_t)h->num_cu * 2);
+                const int64_t useful = std::max<int64_t>(1, per_wg / std::max<int64_t>(1, 4 * len));
+                copies = (int)std::min<int64_t>(std::min<int64_t>(64, fit), std::max<int64_t>(1, useful));
             }
             while (copies > 1 && window_bytes(acc, len, copies) > h->lds_max - p.lds_base)
                 --copies;
