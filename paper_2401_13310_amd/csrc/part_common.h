@@ -68,35 +68,6 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(int64_t total, Get &&ge
     return all;
 }
 
-// Scan pass (one workgroup of 1024 threads) over the events per bucket:
-// bucket j holds slots [bucket_start[j], bucket_start[j+1]), its scatter
-// cursor starts at bucket_start[j], and its records are cut into chunks of at
-// most `chunk`, numbered from chunk_start[j] (chunk count in
-// chunk_start[nbuckets]).
-__device__ __forceinline__ void part_scan(const uint32_t *totals, uint32_t *bucket_start,
-                                          uint32_t *chunk_start, uint32_t *cursor, int nbuckets,
-                                          uint32_t chunk)
-{
-    const uint32_t total = block_exclusive_scan(
-        nbuckets, [&](int64_t j) { return totals[j]; },
-        [&](int64_t j, uint32_t v) {
-            bucket_start[j] = v;
-            cursor[j] = v;
-        });
-    if (threadIdx.x == 0)
-        bucket_start[nbuckets] = total;
-    __syncthreads();
-    const uint32_t chunks = block_exclusive_scan(
-        nbuckets,
-        [&](int64_t j) {
-            const uint32_t r = bucket_start[j + 1] - bucket_start[j];
-            return (r + chunk - 1) / chunk;
-        },
-        [&](int64_t j, uint32_t v) { chunk_start[j] = v; });
-    if (threadIdx.x == 0)
-        chunk_start[nbuckets] = chunks;
-}
-
 // Exclusive prefix sum of one value per thread over the workgroup (wave
 // shuffles, then the wave totals through LDS); `red` is LDS room for the wave
 // totals (kMaxThreads / 64 words).  Returns the prefix; `total` gets the sum.
@@ -131,6 +102,57 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *red, u
     __syncthreads();
     return before + x - v;
 }
+
+// Scan pass (one workgroup of 1024 threads) over the events per bucket:
+// bucket j holds slots [bucket_start[j], bucket_start[j+1]), its scatter
+// cursor starts at bucket_start[j], and its records are cut into chunks of at
+// most `chunk`, numbered from chunk_start[j] (chunk count in
+// chunk_start[nbuckets]).
+__device__ __forceinline__ void part_scan(const uint32_t *totals, uint32_t *bucket_start,
+                                          uint32_t *chunk_start, uint32_t *cursor, int nbuckets,
+                                          uint32_t chunk)
+{
+    if (nbuckets <= (int)blockDim.x) {
+        // one bucket per thread: both prefix sums from one read of the totals
+        __shared__ uint32_t red[16];
+        const int j = threadIdx.x;
+        const uint32_t t = j < nbuckets ? __hip_atomic_load(&totals[j], __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT)
+                                        : 0u;
+        uint32_t all_t, all_c;
+        const uint32_t bs = block_scan_excl(t, red, all_t);
+        const uint32_t cs = block_scan_excl((t + chunk - 1) / chunk, red, all_c);
+        if (j < nbuckets) {
+            bucket_start[j] = bs;
+            cursor[j] = bs;
+            chunk_start[j] = cs;
+        }
+        if (j == 0) {
+            bucket_start[nbuckets] = all_t;
+            chunk_start[nbuckets] = all_c;
+        }
+        return;
+    }
+    const uint32_t total = block_exclusive_scan(
+        nbuckets, [&](int64_t j) { return totals[j]; },
+        [&](int64_t j, uint32_t v) {
+            bucket_start[j] = v;
+            cursor[j] = v;
+        });
+    if (threadIdx.x == 0)
+        bucket_start[nbuckets] = total;
+    __syncthreads();
+    const uint32_t chunks = block_exclusive_scan(
+        nbuckets,
+        [&](int64_t j) {
+            const uint32_t r = bucket_start[j + 1] - bucket_start[j];
+            return (r + chunk - 1) / chunk;
+        },
+        [&](int64_t j, uint32_t v) { chunk_start[j] = v; });
+    if (threadIdx.x == 0)
+        chunk_start[nbuckets] = chunks;
+}
+
 
 // Scatter of the events [begin, end) of range `col`: the range reserves its
 // slots in every bucket with one atomic add on the bucket's cursor (ranges
