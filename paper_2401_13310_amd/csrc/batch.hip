@@ -188,9 +188,15 @@ batch_part_scan_kernel(const MemberDev *__restrict__ members, const int32_t *__r
 }
 
 __global__ void __launch_bounds__(kMaxThreads)
-batch_part_scatter_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ ptiles)
+batch_part_scatter_kernel(const MemberDev *__restrict__ members, const TileDev *__restrict__ ptiles,
+                          uint32_t *totals, int ntotals)
 {
     extern __shared__ __align__(16) char smem[];
+    // the scan has read every member's bucket totals: clear them for the next
+    // replay's count tiles (the batch starts with them zero)
+    if (blockIdx.x == 0)
+        for (int j = threadIdx.x; j < ntotals; j += blockDim.x)
+            totals[j] = 0u;
     const TileDev tile = ptiles[blockIdx.x];
     ConstMember &M = *(ConstMember *)(members + tile.member);
     const int64_t end = tile.start + tile.len;
@@ -292,11 +298,6 @@ static void batch_free(hist_batch_s *b)
 
 static hipError_t batch_enqueue(hist_batch_s *b, hipStream_t s)
 {
-    if (b->npart > 0) {
-        const hipError_t ez = launch_zero_u32(b->d_totals, b->ntotals, s);
-        if (ez != hipSuccess)
-            return ez;
-    }
     hipLaunchKernelGGL(batch_kernel, dim3(b->blocks), dim3(b->threads), (size_t)b->lds, s,
                        b->d_members, b->d_fargs, b->d_variants, b->d_tiles, b->ntiles, b->d_queue);
     hipError_t e = hipGetLastError();
@@ -305,7 +306,7 @@ static hipError_t batch_enqueue(hist_batch_s *b, hipStream_t s)
     hipLaunchKernelGGL(batch_part_scan_kernel, dim3(b->npart), dim3(1024), 0, s, b->d_members,
                        b->d_part_members);
     hipLaunchKernelGGL(batch_part_scatter_kernel, dim3(b->nptiles), dim3(1024), (size_t)b->scatter_lds,
-                       s, b->d_members, b->d_ptiles);
+                       s, b->d_members, b->d_ptiles, b->d_totals, (int)b->ntotals);
     hipLaunchKernelGGL(batch_part_accum_kernel, dim3(b->nchunks), dim3(1024), (size_t)b->accum_lds,
                        s, b->d_members, b->d_chunks);
     return hipGetLastError();
@@ -498,6 +499,8 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         e = hipMalloc(&b->d_part, part_bytes);
         if (e == hipSuccess)
             e = hipMalloc(&b->d_totals, sizeof(uint32_t) * (size_t)b->ntotals);
+        if (e == hipSuccess)
+            e = hipMemset(b->d_totals, 0, sizeof(uint32_t) * (size_t)b->ntotals);
         if (e == hipSuccess)
             e = hipMalloc(&b->d_part_members, sizeof(int32_t) * part_members.size());
         if (e == hipSuccess)

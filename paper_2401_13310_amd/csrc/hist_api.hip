@@ -328,6 +328,7 @@ static hist_status ensure_part(hist_s *h, size_t bytes, hipStream_t s)
     }
     h->d_part = p;
     h->part_bytes = bytes;
+    h->part_zero_at = nullptr;
     return HIST_OK;
 }
 
@@ -391,13 +392,19 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
         c.part_table = P.table;
         c.part_totals = P.totals;
         c.part_shift = b;
-        HIPCHK(launch_zero_u32(P.totals, nb, s), "partition totals reset");
+        // a fill that ran its scatter pass left these totals zero
+        const bool clean = h->part_zero_at == P.totals && nb <= h->part_zero_n;
+        h->part_zero_at = nullptr;
+        if (!clean)
+            HIPCHK(launch_zero_u32(P.totals, nb, s), "partition totals reset");
         HIPCHK(launch_fill(h->dims, f32, ACC_PCOUNT, weighted, p.threads, g, (size_t)p.lds, c, s),
                "partition count launch");
         HIPCHK(launch_part_scan(P, s), "partition scan launch");
         HIPCHK(launch_part_scatter(f32, weighted, kMaxThreads, g, (size_t)part_scatter_lds(nb, weighted),
                                    c, P, s),
                "partition scatter launch");
+        h->part_zero_at = P.totals;
+        h->part_zero_n = nb;
         // every bucket has at most ceil(records / kPartChunk) chunks
         const int chunks_max = nb + (int)((m + kPartChunk - 1) / kPartChunk);
         HIPCHK(launch_part_accum(weighted, 1024, chunks_max, acc_lds, c, P, s),

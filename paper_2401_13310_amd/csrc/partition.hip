@@ -35,6 +35,11 @@ template <typename T, bool W>
 __global__ void __launch_bounds__(kMaxThreads, W ? 4 : 8) part_scatter_kernel(const FillArgs A, PartArgs P)
 {
     extern __shared__ __align__(16) char smem[];
+    // the scan has read the bucket totals: clear them for the next count pass
+    // (so no separate clearing launch precedes it)
+    if (blockIdx.x == 0)
+        for (int j = threadIdx.x; j < P.nbuckets; j += blockDim.x)
+            P.totals[j] = 0u;
     const int64_t start = (int64_t)blockIdx.x * A.per_block;
     const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
     part_scatter<T, W>(A.gbins, static_cast<const T *>(A.w), start, end, P.table, P.cursor,

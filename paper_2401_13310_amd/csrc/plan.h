@@ -71,6 +71,10 @@ struct hist_s {
     int64_t gbins_cap = 0;
     void *d_part = nullptr;                              // PART scratch
     size_t part_bytes = 0;
+    // PART bucket totals known to be zero (the scatter pass clears them):
+    // where they are and how many
+    const void *part_zero_at = nullptr;
+    int part_zero_n = 0;
     int64_t entries = 0;
     hg::PlanChoice forced;                               // hist_set_strategy
     // kernel timing (hist_timing): event pairs around the fill and merge kernels
