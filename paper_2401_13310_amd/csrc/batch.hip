@@ -372,7 +372,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     // latency-bound (searches, global atomics) need many tiles to spread over
     // the CUs; LDS members get enough events per tile to amortize the zeroing
     // and merging of their window.
-    constexpr int64_t kPartTile = 32768;          // events per count / scatter tile
+    constexpr int64_t kPartTile = 65536;          // events per count / scatter tile
     constexpr int64_t kPartMinEvents = 4096;      // fewer events: global atomics
     int max_window_bytes = 0;
     for (int i = 0; i < k; ++i) {
@@ -475,7 +475,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         // tiles: LDS members get enough events per tile to amortize the
         // zeroing and merging of their window
         const int64_t tile_len =
-            m.acc >= 0 ? std::max<int64_t>(32768, 8 * (int64_t)m.win_len * m.copies) : 16384;
+            m.acc >= 0 ? std::max<int64_t>(65536, 8 * (int64_t)m.win_len * m.copies) : 16384;
         const int64_t nt = (d.n + tile_len - 1) / tile_len;
         for (int64_t t = 0; t < nt; ++t) {
             const int64_t s0 = d.n * t / nt, s1 = d.n * (t + 1) / nt;
