@@ -1,18 +1,27 @@
 #!/usr/bin/env python3
 """Fill-throughput benchmark of the gfx950 histogram library on one GPU.
 
-Workload (default): the variable-bin 1D fill -- 99,999 log-spaced bins (1e5
-edges on [1e-3, 1e3]), 5e7 events x ~ Exp(1) in binary64, unit weights, seed
-1 -- with the learned find-bin index (binary search is timed beside it).  One
-step is one hist_fill of all 5e7 events: find bin, LDS accumulation, merge and
-the statistics sums, with the inputs already resident in HBM.
+Headline workload (default): the variable-bin 1D fill -- 99,999 log-spaced
+bins (1e5 edges on [1e-3, 1e3]), 5e7 events x ~ Exp(1) in binary64, unit
+weights, seed 1 -- with the learned find-bin index (binary search is timed
+beside it).  One step is one hist_fill of all 5e7 events: find bin, LDS
+accumulation, merge and the statistics sums, with the inputs already resident
+in HBM.
 
-Prints one JSON line (rank 0).  Fields beyond the driver contract:
-  roofline      HBM roofline of the dominant kernel (the fill kernel), with
-                its duration measured by HIP events on its launch stream
+Prints one JSON line.  Fields beyond the driver contract:
+  roofline      HBM roofline of the fill (every kernel of one hist_fill: the
+                fill kernel plus its merge), durations from HIP events on the
+                launch stream
+  parity        the timed plan's result (one more fill after a reset) against
+                the CPU oracle on the same arrays: counts bit-exact, statistics
+                within 1e-12 of max(|value|, sum of |terms|)
   cpu_baseline  the CPU oracle timed on the host on one full step of the same
-                workload (single thread)
+                workload (single thread), with an all-cores run beside it
   bsearch       the same fill with plain binary search on the variable axis
+  configs       the other workloads (plain 1D, correlated 3D, 64 batched
+                histograms, FP32 precision), each with throughput, roofline
+                fraction and parity against the oracle; the FP32 workload also
+                reports its per-bin and per-statistic error against binary64
 """
 from __future__ import annotations
 
@@ -21,12 +30,15 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "fill events/s + HBM GB/s fraction; learned vs bsearch FindBin, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+REL = 1e-12
+CONFIGS = ("C1", "C3", "C4", "C5")
 
 
 def parse():
@@ -36,9 +48,15 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="variable_1d",
                     choices=["variable_1d", "plain_1d", "corr_3d", "precision", "paper_1d",
-                             "batched_64"])
+                             "batched_64"],
+                    help="variable_1d (default) is the headline and also runs --configs; the "
+                         "others time one workload on its own")
+    ap.add_argument("--configs", default=",".join(CONFIGS),
+                    help="comma-separated subset of %s run beside the headline ('' for none)"
+                         % ",".join(CONFIGS))
     ap.add_argument("--events", type=int, default=0, help="override the event count")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu", action="store_true",
+                    help="skip the CPU oracle (baseline and parity)")
     ap.add_argument("--no-bsearch", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="HBM traffic per launch measured with rocprofv3 counters")
@@ -68,6 +86,141 @@ def kernel_source_hash():
     return hs.hexdigest()[:16]
 
 
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------- host side --
+
+def cpu_threads():
+    """Host threads for the all-cores oracle: the process's CPUs, at most 16
+    (the CPU share a one-GPU machine gives a process)."""
+    n = len(os.sched_getaffinity(0))
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_fill(axes, coords, weights, threads):
+    """The CPU oracle over the events, split into `threads` contiguous chunks
+    filled concurrently (the oracle is C called through ctypes, which releases
+    the interpreter lock) and summed in chunk order.  threads=1 is one plain
+    sequential oracle fill.  Returns the histogram and the wall time."""
+    import oracle
+    n = len(coords[0])
+    p = max(1, min(threads, n // 65536 if n >= 65536 else 1))
+    bounds = [n * i // p for i in range(p + 1)]
+
+    def work(i):
+        b0, b1 = bounds[i], bounds[i + 1]
+        o = oracle.Oracle(axes)
+        o.fill([c[b0:b1] for c in coords], None if weights is None else weights[b0:b1])
+        return o.read()
+
+    t0 = time.perf_counter()
+    if p == 1:
+        parts = [work(0)]
+    else:
+        with ThreadPoolExecutor(p) as ex:
+            parts = list(ex.map(work, range(p)))
+    dt = time.perf_counter() - t0
+    sumw = parts[0][0].copy()
+    sumw2 = parts[0][1].copy()
+    stats = parts[0][2].copy()
+    entries = parts[0][3]
+    for sw, sw2, st, en in parts[1:]:
+        sumw += sw
+        sumw2 += sw2
+        stats += st
+        entries += en
+    return {"sumw": sumw, "sumw2": sumw2, "stats": stats, "entries": entries,
+            "seconds": dt, "threads": p, "events": n}
+
+
+def oracle_scale(axes, coords, weights, threads):
+    """Sum of |per-event term| of every statistic (the tolerance scale of
+    statistics that can cancel), over chunks in parallel."""
+    import oracle
+    n = len(coords[0])
+    p = max(1, min(threads, n // 65536 if n >= 65536 else 1))
+    bounds = [n * i // p for i in range(p + 1)]
+
+    def work(i):
+        b0, b1 = bounds[i], bounds[i + 1]
+        return oracle.stats_abs(axes, [c[b0:b1] for c in coords],
+                                None if weights is None else weights[b0:b1])
+
+    with ThreadPoolExecutor(p) as ex:
+        parts = list(ex.map(work, range(p)))
+    out = parts[0].copy()
+    for q in parts[1:]:
+        out += q
+    return out
+
+
+def compare(got, ref, scale, unit):
+    """Parity of one GPU histogram (sumw, sumw2, entries, stats) with the
+    oracle's: unit-weight counts bit-exact, weighted bin sums within 1e-12
+    relative, statistics within 1e-12 of max(|value|, sum of |terms|)."""
+    import numpy as np
+    sumw, sumw2, entries, st = got
+    res = {"entries_equal": bool(entries == ref["entries"])}
+    ok = res["entries_equal"]
+    if unit:
+        ce = bool(np.array_equal(sumw, ref["sumw"]) and np.array_equal(sumw2, ref["sumw2"]))
+        res["counts_equal"] = ce
+        ok = ok and ce
+    else:
+        for name, g, o in (("sumw", sumw, ref["sumw"]), ("sumw2", sumw2, ref["sumw2"])):
+            err = np.abs(g - o)
+            bad = int(np.count_nonzero(err > REL * np.abs(o)))
+            nz = o != 0
+            res[name + "_max_rel_err"] = float(np.max(err[nz] / np.abs(o[nz]))) if nz.any() else 0.0
+            res[name + "_bins_out_of_tolerance"] = bad
+            ok = ok and bad == 0
+    sc = np.maximum(np.abs(ref["stats"]), scale)
+    serr = np.abs(np.asarray(st) - ref["stats"]) / np.where(sc > 0, sc, 1.0)
+    res["stats_max_scaled_err"] = float(np.max(serr))
+    ok = ok and bool(np.all(serr <= REL))
+    res["ok"] = bool(ok)
+    return res
+
+
+def precision_errors(sumw, sumw2, st, ref, scale):
+    """Error of an approximate histogram against the binary64 oracle: per-bin
+    relative error of the sums over bins the oracle fills, per statistic the
+    plain relative error and the error scaled by the sum of |terms|."""
+    import numpy as np
+    out = {}
+    for name, g, o in (("sumw", sumw, ref["sumw"]), ("sumw2", sumw2, ref["sumw2"])):
+        nz = o != 0
+        rel = np.abs(g[nz] - o[nz]) / np.abs(o[nz])
+        out[name + "_bin_rel_err_max"] = float(rel.max()) if rel.size else 0.0
+        out[name + "_bin_rel_err_median"] = float(np.median(rel)) if rel.size else 0.0
+        out[name + "_empty_bins_nonzero"] = int(np.count_nonzero(g[~nz]))
+    o = ref["stats"]
+    g = np.asarray(st)
+    out["stats_rel_err"] = [float(abs(a - b) / abs(b)) if b != 0 else float(abs(a))
+                            for a, b in zip(g, o)]
+    out["stats_scaled_err"] = [float(abs(a - b) / max(abs(b), s)) if max(abs(b), s) > 0 else 0.0
+                               for a, b, s in zip(g, o, scale)]
+    return out
+
+
+# ---------------------------------------------------------------- workloads --
+
 def build_workload(name, events):
     import synth
     if name == "variable_1d":
@@ -79,7 +232,6 @@ def build_workload(name, events):
     if name == "paper_1d":
         return synth.paper_1d(events or 500_000_000 // 10)
     if name == "precision":
-        import numpy as np
         n = events or synth.PRECISION_SLICE
         x, w = next(synth.precision_slices(n=n, slice_len=n))
         return {"name": "precision", "axes": synth.precision_axes(), "coords": [x], "weights": w}
@@ -99,50 +251,304 @@ def describe(wl, n):
     return "%s: %s; %d events, %s, %s" % (wl["name"], " x ".join(parts), n, dt, w)
 
 
+def hist_bytes(axes):
+    """16 T (final sums of weights and squared weights, binary64) plus the
+    edge arrays, each read once."""
+    T = 1
+    edges = 0
+    for a in axes:
+        T *= a["nbins"] + 2
+        if a.get("edges") is not None:
+            edges += (a["nbins"] + 1) * 8
+    return 16 * T + edges
+
+
 def alg_bytes(wl, n):
     """Algorithmic HBM bytes of one fill: every coordinate and weight read
     once, the final sums of weights and squared weights written once (FP64),
     each edge array read once."""
     esz = wl["coords"][0].dtype.itemsize
     per_event = len(wl["coords"]) * esz + (0 if wl["weights"] is None else esz)
-    T = 1
-    edges = 0
-    for a in wl["axes"]:
-        T *= a["nbins"] + 2
-        if a.get("edges") is not None:
-            edges += (a["nbins"] + 1) * 8
-    return per_event * n + 16 * T + edges, per_event
+    return per_event * n + hist_bytes(wl["axes"]), per_event
 
 
-def time_fills(hg, h, cols, w, steps, warmup):
+def to_dev(wl):
+    import torch
+    cols = [torch.from_numpy(c).to("cuda") for c in wl["coords"]]
+    w = None if wl["weights"] is None else torch.from_numpy(wl["weights"]).to("cuda")
+    return cols, w
+
+
+def train_all(h, axes):
+    for a, ax in enumerate(axes):
+        if ax.get("edges") is not None:
+            h.train_index(a)
+
+
+def time_fills(h, step, steps, warmup):
+    """Runs `step` warmup + steps times; returns the wall time of the timed
+    steps and the library's kernel timing (fill and merge kernels, HIP events
+    on the launch stream) summed over them."""
     import torch
     for _ in range(warmup):
-        h.fill(cols, w)
+        step()
     torch.cuda.synchronize()
-    h.timing(True)
+    hs = h if isinstance(h, (list, tuple)) else [h]
+    for x in hs:
+        x.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        h.fill(cols, w)
+        step()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kt = h.timing_read()
-    h.timing(False)
-    return wall, kt
+    fill = merge = 0.0
+    launches = 0
+    for x in hs:
+        kt = x.timing_read()
+        x.timing(False)
+        fill += kt["fill_ms"]
+        merge += kt["merge_ms"]
+        launches += kt["launches"]
+    return wall, {"fill_ms": fill / steps, "merge_ms": merge / steps, "launches": launches / steps}
 
 
-def cpu_baseline(wl, n):
-    import oracle
-    o = oracle.Oracle(wl["axes"])
-    cols = [c.astype("float64") for c in wl["coords"]]
-    w = None if wl["weights"] is None else wl["weights"].astype("float64")
-    t0 = time.perf_counter()
-    o.fill(cols, w)
-    dt = time.perf_counter() - t0
-    return {"value": n / dt, "unit": "events/s", "cores": 1, "kind": "oracle",
-            "sample": "one full step (%d events, same arrays), sequential C oracle, %.2f s"
-                      % (n, dt)}
+def gpu_result(h):
+    sumw, sumw2, entries = h.read()
+    return sumw, sumw2, entries, h.stats()
 
+
+def roofline(bytes_, ms):
+    gbs = bytes_ / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS}
+
+
+def release():
+    import gc
+
+    import torch
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+# ----------------------------------------------------------------- configs ---
+
+def config_single(name, wl, args, threads, flags=0, compare_global=False):
+    """A one-histogram workload: tuned plan timed (and the global-atomic plan
+    beside it), parity of the tuned plan against the oracle."""
+    import paper_2401_13310_amd as hg
+    cols, w = to_dev(wl)
+    n = wl["coords"][0].size
+    h = hg.Hist(wl["axes"], flags)
+    train_all(h, wl["axes"])
+    sample = min(n, 1 << 22)
+    h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
+    plan = h.plan_info(n, hg.HIST_F64, w is not None)
+    wall, kt = time_fills(h, lambda: h.fill(cols, w), args.steps, args.warmup)
+    B, per_event = alg_bytes(wl, n)
+    kms = kt["fill_ms"] + kt["merge_ms"]
+    out = {"workload": describe(wl, n), "plan": plan, "value": n * args.steps / wall,
+           "unit": "events/s", "ms_per_step": wall / args.steps * 1e3, "kernel_ms": kms,
+           "roofline": dict(roofline(B, kms), alg_bytes_per_launch=B)}
+    if compare_global:
+        hgb = hg.Hist(wl["axes"], flags)
+        hgb.set_strategy(hg.HIST_STRAT_GLOBAL)
+        sb = max(3, args.steps // 4)
+        wall_g, kt_g = time_fills(hgb, lambda: hgb.fill(cols, w), sb, 1)
+        kg = kt_g["fill_ms"] + kt_g["merge_ms"]
+        out["global_atomics"] = {"value": n * sb / wall_g, "ms_per_step": wall_g / sb * 1e3,
+                                 "kernel_ms": kg, "frac": roofline(B, kg)["frac"]}
+        out["tuned_speedup_vs_global"] = out["value"] / out["global_atomics"]["value"]
+        hgb.close()
+    if not args.no_cpu:
+        h.reset()
+        h.fill(cols, w)
+        got = gpu_result(h)
+        ref = oracle_fill(wl["axes"], wl["coords"], wl["weights"], threads)
+        scale = oracle_scale(wl["axes"], wl["coords"], wl["weights"], threads)
+        out["parity"] = compare(got, ref, scale, wl["weights"] is None)
+        out["cpu_oracle"] = {"value": n / ref["seconds"], "unit": "events/s",
+                             "cores": ref["threads"]}
+    h.close()
+    del cols, w
+    release()
+    return out
+
+
+def config_batched(args, threads):
+    """64 uneven histograms: one graph replay of the persistent batch kernel,
+    against 64 separate plain fills (binary search, global atomics) and 64
+    separate default fills."""
+    import torch
+
+    import paper_2401_13310_amd as hg
+    import synth
+
+    members = synth.batched_64()
+    cols, ws, nev, B = [], [], 0, 0
+    for m in members:
+        cols.append([torch.from_numpy(c).to("cuda") for c in m["coords"]])
+        ws.append(torch.from_numpy(m["weights"]).to("cuda"))
+        n = m["weights"].size
+        nev += n
+        B += n * 8 * (len(m["axes"]) + 1) + hist_bytes(m["axes"])
+
+    def make(learned):
+        hs = []
+        for m in members:
+            h = hg.Hist(m["axes"])
+            if learned:
+                train_all(h, m["axes"])
+            hs.append(h)
+        return hs
+
+    def timed(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    hs = make(True)
+    batch = hg.Batch(hs, cols, ws)
+    ms_graph = timed(lambda: batch.launch(graph=True), args.steps, args.warmup)
+    plain = make(False)
+    for h in plain:
+        h.set_strategy(hg.HIST_STRAT_GLOBAL)
+    sp = max(2, args.steps // 4)
+    ms_plain = timed(lambda: [h.fill(c, w) for h, c, w in zip(plain, cols, ws)], sp, 1)
+    deflt = make(True)
+    ms_default = timed(lambda: [h.fill(c, w) for h, c, w in zip(deflt, cols, ws)], sp, 1)
+    out = {"workload": "batched_64: 64 histograms, dims 1-3, log-uniform bins and events, "
+                       "%d events, FP64 coordinates and weights" % nev,
+           "value": nev / (ms_graph * 1e-3), "unit": "events/s", "ms_per_step": ms_graph,
+           "kernel_ms": ms_graph,
+           "roofline": dict(roofline(B, ms_graph), alg_bytes_per_launch=B,
+                            kernel="batch graph (persistent kernel + partition passes)"),
+           "plain_fills": {"value": nev / (ms_plain * 1e-3), "ms_per_step": ms_plain,
+                           "what": "64 hist_fill calls, binary search, global atomics"},
+           "default_fills": {"value": nev / (ms_default * 1e-3), "ms_per_step": ms_default,
+                             "what": "64 hist_fill calls, learned index, heuristic plans"},
+           "speedup_vs_plain": ms_plain / ms_graph}
+    for h in plain + deflt:
+        h.close()
+    if not args.no_cpu:
+        for h in hs:
+            h.reset()
+        batch.launch(graph=True)
+        torch.cuda.synchronize()
+        got = [gpu_result(h) for h in hs]
+
+        def ref_of(i):
+            m = members[i]
+            r = oracle_fill(m["axes"], m["coords"], m["weights"], 1)
+            s = oracle_scale(m["axes"], m["coords"], m["weights"], 1)
+            return r, s
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(threads) as ex:
+            refs = list(ex.map(ref_of, range(len(members))))
+        dt = time.perf_counter() - t0
+        per = [compare(g, r, s, False) for g, (r, s) in zip(got, refs)]
+        out["parity"] = {"members": len(per), "members_ok": sum(p["ok"] for p in per),
+                         "ok": all(p["ok"] for p in per),
+                         "sumw_max_rel_err": max(p["sumw_max_rel_err"] for p in per),
+                         "stats_max_scaled_err": max(p["stats_max_scaled_err"] for p in per)}
+        out["cpu_oracle"] = {"value": nev / dt, "unit": "events/s", "cores": threads,
+                             "what": "one oracle per member, members in parallel (with the "
+                                     "statistics-scale pass)"}
+    batch.close()
+    for h in hs:
+        h.close()
+    del cols, ws
+    release()
+    return out
+
+
+def config_precision(args, threads):
+    """2e8 FP32 events in 12 slices of 2^24 into 1e4 fixed bins: the
+    compensated FP32 accumulator against the all-binary64 path on the same
+    values widened, both against the binary64 oracle."""
+    import numpy as np
+    import torch
+
+    import paper_2401_13310_amd as hg
+    import synth
+
+    axes = synth.precision_axes()
+    slices = list(synth.precision_slices())
+    n = sum(x.size for x, _ in slices)
+    xs32 = [torch.from_numpy(x).to("cuda") for x, _ in slices]
+    ws32 = [torch.from_numpy(w).to("cuda") for _, w in slices]
+    xs64 = [x.double() for x in xs32]
+    ws64 = [w.double() for w in ws32]
+    out = {"workload": "precision: 10000 fixed bins [0, 100); %d events x ~ Gamma(2, 10), "
+                       "w ~ LogNormal(0, 2), FP32, %d slices of up to 2^24" % (n, len(slices))}
+    hs = {}
+    for key, flags, xs, ws, esz in (("f32c", hg.HIST_F_ACC_F32C, xs32, ws32, 4),
+                                    ("f64", 0, xs64, ws64, 8)):
+        h = hg.Hist(axes, flags)
+        sample = min(xs[0].numel(), 1 << 22)
+        h.tune([xs[0][:sample]], ws[0][:sample])
+
+        def step(h=h, xs=xs, ws=ws):
+            for x, w in zip(xs, ws):
+                h.fill([x], w)
+
+        steps = max(3, args.steps // 4)
+        wall, kt = time_fills(h, step, steps, 1)
+        B = n * 2 * esz + 12 * hist_bytes(axes)
+        kms = kt["fill_ms"] + kt["merge_ms"]
+        out[key] = {"value": n * steps / wall, "unit": "events/s",
+                    "ms_per_step": wall / steps * 1e3, "kernel_ms": kms,
+                    "roofline": dict(roofline(B, kms), alg_bytes_per_launch=B),
+                    "plan": h.plan_info(xs[0].numel(), hg.HIST_F32 if esz == 4 else hg.HIST_F64,
+                                        True)}
+        hs[key] = (h, step)
+    out["f32c_speedup_vs_f64"] = out["f32c"]["value"] / out["f64"]["value"]
+    if not args.no_cpu:
+        # the binary64 oracle on the widened values, one oracle per slice
+        def work(i):
+            x, w = slices[i]
+            r = oracle_fill(axes, [x], w, 1)
+            s = oracle_scale(axes, [x], w, 1)
+            return r, s
+
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(min(threads, len(slices))) as ex:
+            parts = list(ex.map(work, range(len(slices))))
+        dt = time.perf_counter() - t0
+        ref = {"sumw": sum(p[0]["sumw"] for p in parts), "sumw2": sum(p[0]["sumw2"] for p in parts),
+               "stats": sum(p[0]["stats"] for p in parts),
+               "entries": sum(p[0]["entries"] for p in parts)}
+        scale = sum(p[1] for p in parts)
+        out["cpu_oracle"] = {"value": n / dt, "unit": "events/s",
+                             "cores": min(threads, len(slices))}
+        for key, (h, step) in hs.items():
+            h.reset()
+            step()
+            got = gpu_result(h)
+            out[key]["errors_vs_fp64_oracle"] = precision_errors(got[0], got[1], got[3], ref,
+                                                                 scale)
+            if key == "f64":
+                out[key]["parity"] = compare(got, ref, scale, False)
+            else:
+                out[key]["entries_equal"] = bool(got[2] == ref["entries"])
+    for h, _ in hs.values():
+        h.close()
+    del xs32, ws32, xs64, ws64
+    release()
+    return out
+
+
+# ------------------------------------------------------- counter ingestion --
 
 def load_traffic(path, workload, n, plan):
     """HBM bytes per fill launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy
@@ -226,104 +632,21 @@ def ingest(args):
     print(json.dumps(rec))
 
 
-def bench_batched(args):
-    """64 uneven histograms: one graph replay of the persistent batch kernel
-    against 64 separate plain fills (binary search, global atomics) and 64
-    separate default fills."""
-    import numpy as np
-    import torch
+# -------------------------------------------------------------------- main ---
 
-    import paper_2401_13310_amd as hg
-    import synth
-
-    members = synth.batched_64(n_scale=1.0 if not args.events else args.events / 9.3e7)
-    cols, ws, nev, B = [], [], 0, 0
-    for m in members:
-        cols.append([torch.from_numpy(c).to("cuda") for c in m["coords"]])
-        ws.append(torch.from_numpy(m["weights"]).to("cuda"))
-        n = m["weights"].size
-        nev += n
-        T = 1
-        for a in m["axes"]:
-            T *= a["nbins"] + 2
-            if a.get("edges") is not None:
-                B += 8 * (a["nbins"] + 1)
-        B += n * 8 * (len(m["axes"]) + 1) + 16 * T
-
-    def make(learned):
-        hs = []
-        for m in members:
-            h = hg.Hist(m["axes"])
-            if learned:
-                for a, ax in enumerate(m["axes"]):
-                    if ax.get("edges") is not None:
-                        h.train_index(a)
-            hs.append(h)
-        return hs
-
-    def timed(fn, steps, warmup):
-        for _ in range(warmup):
-            fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
-    hs = make(True)
-    batch = hg.Batch(hs, cols, ws)
-    ms_graph = timed(lambda: batch.launch(graph=True), args.steps, args.warmup)
-    plain = make(False)
-    for h in plain:
-        h.set_strategy(hg.HIST_STRAT_GLOBAL)
-    ms_plain = timed(lambda: [h.fill(c, w) for h, c, w in zip(plain, cols, ws)], max(2, args.steps // 4), 1)
-    deflt = make(True)
-    ms_default = timed(lambda: [h.fill(c, w) for h, c, w in zip(deflt, cols, ws)], max(2, args.steps // 4), 1)
-    value = nev / (ms_graph * 1e-3)
-    out = {
-        "metric": METRIC, "value": value, "unit": "events/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_graph, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic (seeded numpy PCG64)",
-        "config": {"workload": "batched_64: 64 histograms, dims 1-3, log-uniform bins and events, "
-                               "%d events, FP64 weights" % nev},
-        "roofline": {"bound": "hbm", "achieved": B / (ms_graph * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": B / (ms_graph * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                     "traffic": None, "kernel": "batch_kernel", "alg_bytes_per_launch": B},
-        "plain_fills": {"value": nev / (ms_plain * 1e-3), "ms_per_step": ms_plain,
-                        "what": "64 hist_fill calls, binary search, global atomics"},
-        "default_fills": {"value": nev / (ms_default * 1e-3), "ms_per_step": ms_default,
-                          "what": "64 hist_fill calls, learned index, heuristic plans"},
-        "speedup_vs_plain": ms_plain / ms_graph,
-    }
-    print(json.dumps(out), flush=True)
-
-
-def main():
-    args = parse()
-    if args.ingest:
-        ingest(args)
-        return
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X; "
-              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def run_single(args, wl, headline):
+    """Times one workload (the headline runs its configs and CPU legs too)."""
     import numpy as np
     import torch
 
     import paper_2401_13310_amd as hg
 
-    torch.cuda.set_device(0)
-    if args.workload == "batched_64":
-        bench_batched(args)
-        return
-    wl = build_workload(args.workload, args.events)
     n = wl["coords"][0].size
-    cols = [torch.from_numpy(c).to("cuda") for c in wl["coords"]]
-    w = None if wl["weights"] is None else torch.from_numpy(wl["weights"]).to("cuda")
-    flags = hg.HIST_F_ACC_F32C if args.workload == "precision" else 0
+    threads = cpu_threads()
+    log("workload %s, %d events" % (wl["name"], n))
+    cols, w = to_dev(wl)
+    f32 = wl["coords"][0].dtype == np.float32
+    flags = hg.HIST_F_ACC_F32C if wl["name"] == "precision" else 0
     variable = any(a.get("edges") is not None for a in wl["axes"])
 
     h = hg.Hist(wl["axes"], flags)
@@ -331,15 +654,12 @@ def main():
     if variable:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for a, ax in enumerate(wl["axes"]):
-            if ax.get("edges") is not None:
-                h.train_index(a)
+        train_all(h, wl["axes"])
         torch.cuda.synchronize()
         train_ms = (time.perf_counter() - t0) * 1e3
     sample = min(n, 1 << 22)
     h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
-    plan = h.plan_info(n, hg.HIST_F32 if wl["coords"][0].dtype == np.float32 else hg.HIST_F64,
-                       w is not None)
+    plan = h.plan_info(n, hg.HIST_F32 if f32 else hg.HIST_F64, w is not None)
     if args.profile:
         for _ in range(args.steps):
             h.fill(cols, w)
@@ -360,17 +680,19 @@ def main():
         h.close()
         return
 
-    wall, kt = time_fills(hg, h, cols, w, args.steps, args.warmup)
+    wall, kt = time_fills(h, lambda: h.fill(cols, w), args.steps, args.warmup)
+    log("timed %d steps: %.4f ms/step" % (args.steps, wall / args.steps * 1e3))
     ms_step = wall / args.steps * 1e3
     value = n * args.steps / wall
-    fill_ms = kt["fill_ms"] / max(1, kt["launches"])
-    if fill_ms <= 0:
-        fill_ms = ms_step
-    merge_ms = kt["merge_ms"] / max(1, kt["launches"])
+    fill_ms = kt["fill_ms"] / max(1.0, kt["launches"]) if kt["launches"] else ms_step
+    merge_ms = kt["merge_ms"] / max(1.0, kt["launches"]) if kt["launches"] else 0.0
+    kernel_ms = fill_ms + merge_ms
     B, per_event = alg_bytes(wl, n)
-    achieved = B / (fill_ms * 1e-3) / 1e9
     traffic = load_traffic(args.traffic, args.workload, n, plan)
-
+    rl = roofline(B, kernel_ms)
+    rl.update({"traffic": traffic, "kernel": "fill_kernel + its merge kernel (one hist_fill)",
+               "kernel_ms": kernel_ms, "fill_kernel_ms": fill_ms, "merge_kernel_ms": merge_ms,
+               "alg_bytes_per_launch": B, "alg_bytes_per_event": per_event})
     out = {
         "metric": METRIC,
         "value": value,
@@ -382,16 +704,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if wl["coords"][0].dtype == np.float32 else "f64",
+        "dtype": "f32" if f32 else "f64",
         "data": "synthetic (seeded numpy PCG64), resident in HBM before timing",
         "config": {"workload": describe(wl, n),
                    "search": "learned" if variable else "fixed-width formula",
                    "plan": plan},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fill_kernel", "kernel_ms": fill_ms,
-                     "merge_kernel_ms": merge_ms,
-                     "alg_bytes_per_launch": B, "alg_bytes_per_event": per_event},
+        "roofline": rl,
         "step_hbm_frac": B / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
     }
     if train_ms is not None:
@@ -399,17 +717,91 @@ def main():
     if variable and not args.no_bsearch:
         hb = hg.Hist(wl["axes"], flags)
         hb.tune([c[:sample] for c in cols], None if w is None else w[:sample])
-        wall_b, kt_b = time_fills(hg, hb, cols, w, max(3, args.steps // 2), 1)
         steps_b = max(3, args.steps // 2)
+        wall_b, kt_b = time_fills(hb, lambda: hb.fill(cols, w), steps_b, 1)
         out["bsearch"] = {"value": n * steps_b / wall_b, "ms_per_step": wall_b / steps_b * 1e3,
-                          "kernel_ms": kt_b["fill_ms"] / max(1, kt_b["launches"]),
+                          "kernel_ms": kt_b["fill_ms"] / max(1.0, kt_b["launches"]) +
+                          kt_b["merge_ms"] / max(1.0, kt_b["launches"]),
                           "plan": hb.plan_info(n, hg.HIST_F64, w is not None)}
         out["learned_speedup_vs_bsearch"] = out["value"] / out["bsearch"]["value"]
         hb.close()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(wl, n)
+        # the timed plan's result: one more fill after a reset
+        h.reset()
+        h.fill(cols, w)
+        got = gpu_result(h)
+        log("CPU oracle, one thread, %d events" % n)
+        ref = oracle_fill(wl["axes"], wl["coords"], wl["weights"], 1)
+        log("CPU oracle, %d threads" % threads)
+        ref_all = oracle_fill(wl["axes"], wl["coords"], wl["weights"], threads)
+        scale = oracle_scale(wl["axes"], wl["coords"], wl["weights"], threads)
+        out["parity"] = compare(got, ref, scale, w is None)
+        out["parity"]["what"] = ("the timed plan (reset, one fill) against the sequential oracle "
+                                 "on the same %d events" % n)
+        out["cpu_baseline"] = {
+            "value": n / ref["seconds"], "unit": "events/s", "cores": 1, "kind": "oracle",
+            "sample": "one full step (%d events, the same arrays), sequential C oracle, %.2f s"
+                      % (n, ref["seconds"]),
+            "cpu_model": cpu_model(),
+            "all_cores": {"value": n / ref_all["seconds"], "unit": "events/s",
+                          "cores": ref_all["threads"],
+                          "what": "the same oracle on %d contiguous chunks in parallel threads, "
+                                  "summed in chunk order, %.2f s"
+                                  % (ref_all["threads"], ref_all["seconds"]),
+                          "counts_equal_sequential": bool(
+                              np.array_equal(ref_all["sumw"], ref["sumw"]))},
+        }
     h.close()
+    del cols, w
+    release()
+    if headline:
+        threads = cpu_threads()
+        wanted = [c.strip() for c in args.configs.split(",") if c.strip()]
+        configs = {}
+        for c in wanted:
+            log("config %s" % c)
+            try:
+                if c == "C1":
+                    configs["C1_plain_1d"] = config_single("C1", build_workload("plain_1d", 0),
+                                                           args, threads)
+                elif c == "C3":
+                    configs["C3_corr_3d"] = config_single("C3", build_workload("corr_3d", 0), args,
+                                                          threads, compare_global=True)
+                elif c == "C4":
+                    configs["C4_batched_64"] = config_batched(args, threads)
+                elif c == "C5":
+                    configs["C5_precision"] = config_precision(args, threads)
+                else:
+                    raise SystemExit("unknown config %s" % c)
+            except (RuntimeError, ValueError, MemoryError) as e:
+                configs[c] = {"error": "%s: %s" % (type(e).__name__, e)}
+            log("config %s done" % c)
+        if configs:
+            out["configs"] = configs
     print(json.dumps(out), flush=True)
+
+
+def main():
+    args = parse()
+    if args.ingest:
+        ingest(args)
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    if args.workload == "batched_64":
+        out = config_batched(args, cpu_threads())
+        out.update({"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                    "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                    "dtype": "f64", "data": "synthetic (seeded numpy PCG64)",
+                    "config": {"workload": out.pop("workload")}})
+        print(json.dumps(out), flush=True)
+        return
+    run_single(args, build_workload(args.workload, args.events),
+               headline=args.workload == "variable_1d" and not args.events)
 
 
 if __name__ == "__main__":

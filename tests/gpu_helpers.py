@@ -21,6 +21,22 @@ def dev(a, dtype=None):
     return t.to("cuda")
 
 
+def _fingerprint(got, want):
+    """Where two histograms differ, in terms that tell failure kinds apart:
+    events lost (bins only low, total short), events mis-binned (as many
+    units gained as lost, total unchanged) or extra events (total long)."""
+    d = np.asarray(got, dtype=np.float64) - np.asarray(want, dtype=np.float64)
+    hi = np.nonzero(d > 0)[0]
+    lo = np.nonzero(d < 0)[0]
+    return ("%d bins high (+%.6g), %d bins low (%.6g); total got %.17g want %.17g "
+            "(diff %.6g); first high %s, first low %s"
+            % (hi.size, float(d[hi].sum()) if hi.size else 0.0, lo.size,
+               float(d[lo].sum()) if lo.size else 0.0, math.fsum(np.asarray(got, np.float64)),
+               math.fsum(np.asarray(want, np.float64)),
+               math.fsum(np.asarray(got, np.float64)) - math.fsum(np.asarray(want, np.float64)),
+               hi[:8].tolist(), lo[:8].tolist()))
+
+
 def assert_bins_equal(got, want, what="bins"):
     got = np.asarray(got)
     want = np.asarray(want)
@@ -28,8 +44,9 @@ def assert_bins_equal(got, want, what="bins"):
     bad = np.nonzero(got != want)[0]
     if bad.size:
         i = bad[0]
-        raise AssertionError("%s differ at %d of %d places; first at %d: got %d want %d"
-                             % (what, bad.size, got.size, i, got[i], want[i]))
+        raise AssertionError("%s differ at %d of %d places; first at %d: got %d want %d; %s"
+                             % (what, bad.size, got.size, i, got[i], want[i],
+                                _fingerprint(got, want)))
 
 
 def assert_sums_close(got, want, rel=REL, what="sums"):
@@ -40,9 +57,12 @@ def assert_sums_close(got, want, rel=REL, what="sums"):
     bad = np.nonzero(err > lim)[0]
     if bad.size:
         i = bad[0]
-        raise AssertionError("%s differ at %d bins; first at %d: got %r want %r (rel %.3g)"
+        raise AssertionError("%s differ at %d bins; first at %d: got %r want %r (rel %.3g); "
+                             "largest rel %.3g; %s"
                              % (what, bad.size, i, got[i], want[i],
-                                err[i] / max(abs(want[i]), 1e-300)))
+                                err[i] / max(abs(want[i]), 1e-300),
+                                float(np.max(err[bad] / np.maximum(np.abs(want[bad]), 1e-300))),
+                                _fingerprint(got, want)))
 
 
 def assert_stats_close(got, want, abs_scale, rel=REL):

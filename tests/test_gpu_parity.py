@@ -36,6 +36,11 @@ def gpu_findbin(hg, axes, cols, learned=False, dtype=None):
     return out, h
 
 
+def _assert(cond, msg):
+    if not cond:
+        raise AssertionError(msg)
+
+
 def fill_and_compare(hg, axes, coords, w, strategy=None, flags=0, learned=False, dtype=None,
                      window=None, blocks=0, copies=0, check_sums=True):
     import torch
@@ -60,16 +65,29 @@ def fill_and_compare(hg, axes, coords, w, strategy=None, flags=0, learned=False,
                                  torch.tensor(w).to(dtype).double().numpy())
     o.fill(oc, ow)
     osw, osw2, ost, oent = o.read()
-    assert entries == oent
-    if w is None:
-        assert_bins_equal(sumw, osw, "unit-weight counts")
-        assert_bins_equal(sumw2, osw2, "unit-weight counts (sumw2)")
-    elif check_sums:
-        assert_sums_close(sumw, osw, what="sumw")
-        assert_sums_close(sumw2, osw2, what="sumw2")
     scale = oracle.stats_abs(axes, oc, ow)
+    # every check runs and every failure is reported together, so that a
+    # failure tells lost events (bins low, totals and statistics short) from
+    # mis-binned ones (as much gained as lost, statistics intact)
+    failures = []
+
+    def collect(check, *args, **kw):
+        try:
+            check(*args, **kw)
+        except AssertionError as e:
+            failures.append(str(e))
+
+    collect(lambda: _assert(entries == oent, "entries %d want %d" % (entries, oent)))
+    if w is None:
+        collect(assert_bins_equal, sumw, osw, "unit-weight counts")
+        collect(assert_bins_equal, sumw2, osw2, "unit-weight counts (sumw2)")
+    elif check_sums:
+        collect(assert_sums_close, sumw, osw, what="sumw")
+        collect(assert_sums_close, sumw2, osw2, what="sumw2")
     if check_sums:
-        assert_stats_close(st, ost, scale)
+        collect(assert_stats_close, st, ost, scale)
+    if failures:
+        raise AssertionError("; ".join(failures) + "; stats got %r want %r" % (list(st), list(ost)))
     torch.cuda.synchronize()
     return h, (sumw, sumw2, st, entries), (osw, osw2, ost, oent)
 
