@@ -28,7 +28,8 @@
  *   - Streams are hipStream_t values passed as void* (NULL = null stream).
  *     Calls marked "asynchronous" enqueue work on the stream and return; the
  *     caller keeps every input buffer alive and unmodified until the stream
- *     has passed the call.  They never synchronize the device.
+ *     has passed the call.  They never synchronize the device (hist_fill only
+ *     when it must grow its scratch, see there).
  *   - Device pointers are plain HIP device addresses (e.g. a torch tensor's
  *     data_ptr()).  Host pointers are ordinary process memory.
  *   - Every function returns a hist_status; on error the handle is left as it
@@ -80,6 +81,9 @@ typedef struct {
                                         accumulated in FP64 like FP64 inputs        */
 #define HIST_F_LEARNED    (1u << 1)  /* train the learned find-bin index of every
                                         variable axis at creation (hist_train_index) */
+#define HIST_F_NO_ALLOC   (1u << 2)  /* fills never allocate: a fill whose plan needs
+                                        more scratch than hist_reserve set aside fails
+                                        with HIST_ENOMEM instead of growing it       */
 
 /* Accumulation strategies (hist_set_strategy / hist_plan_info).  */
 typedef enum {
@@ -107,7 +111,8 @@ typedef enum {
 /* ---- lifecycle ---------------------------------------------------------- */
 
 /* Creates a histogram on the current HIP device.  dims in 1..3, axes[dims].
- * Allocates and zeroes the device bin arrays, statistics and scratch.
+ * Allocates and zeroes the device bin arrays, statistics and entry count
+ * (scratch comes from hist_reserve or the first fill that needs it).
  * Errors: HIST_EINVAL (bad axes, T > 2^31-1, out == NULL), HIST_ENOMEM,
  * HIST_EDEVICE.  Synchronizes the device once (creation is not a hot call). */
 HIST_API hist_status hist_create(int dims, const hist_axis *axes, uint32_t flags, hist_t **out);
@@ -120,13 +125,34 @@ HIST_API hist_status hist_destroy(hist_t *h);
 /* Fill n events (Sec. 3.1 steps 1-3), adding to earlier fills (Sec. 3.3).
  * coords: HOST array of dims DEVICE pointers; coords[a][i] is coordinate a of
  * event i, n contiguous values of `dtype` each.  weights: DEVICE pointer to n
- * values of `dtype`, or NULL for unit weights.  n == 0 is a no-op.
- * Asynchronous on `stream`; allocates nothing; capture-safe.
- * Errors: HIST_EINVAL (NULL handle, n < 0, NULL coordinate with n > 0,
- * HIST_F32C accumulation requested with FP64 inputs is not an error -- FP64
- * inputs always accumulate in FP64), HIST_EDEVICE (launch failure). */
+ * values of `dtype`, or NULL for unit weights.  n == 0 is a no-op.  The entry
+ * count is kept on the device and grows by n when the fill runs, so fills
+ * captured into a graph count once per replay.
+ * Asynchronous on `stream`, launches kernels only (no memset, no copy).
+ * Scratch: plans for histograms larger than LDS use the handle's scratch
+ * memory (the staging slots of a merged LDS window, the bin array and tables
+ * of the tiled and partitioned strategies).  When it is smaller than the plan
+ * needs, the fill first grows it -- hipMalloc, and a synchronization of
+ * `stream` before the old buffer is freed -- except during stream capture
+ * (HIST_ECAPTURE) and for handles created with HIST_F_NO_ALLOC (HIST_ENOMEM).
+ * After hist_reserve(n_max, ...) fills of up to n_max events allocate and
+ * synchronize nothing and are capture-safe.
+ * Errors: HIST_EINVAL (NULL handle, n < 0, NULL coordinate with n > 0;
+ * HIST_F_ACC_F32C with FP64 inputs is not an error -- FP64 inputs always
+ * accumulate in FP64), HIST_ENOMEM, HIST_ECAPTURE (scratch too small, see
+ * above), HIST_EDEVICE (launch failure). */
 HIST_API hist_status hist_fill(hist_t *h, const void *const *coords, const void *weights,
                       int64_t n, hist_dtype dtype, void *stream);
+
+/* Sizes the handle's scratch for fills of 1..n_max events of `dtype`, with
+ * weights (weighted != 0) or without, under the plan choice in force (forced
+ * strategy, tuned plan or heuristic): afterwards such fills allocate nothing.
+ * A later hist_set_strategy, hist_set_window, hist_set_threads or hist_tune
+ * may select plans that need more.  Allocates, synchronizes `stream`;
+ * HIST_ECAPTURE while capturing.  Errors: HIST_EINVAL (n_max < 0),
+ * HIST_ENOMEM. */
+HIST_API hist_status hist_reserve(hist_t *h, int64_t n_max, hist_dtype dtype, int weighted,
+                                  void *stream);
 
 /* Find-bin only (Sec. 3.1 step 1 plus the global-bin linearization): writes
  * the global bin of each event to bins_dev (DEVICE, n int32).  Same search
@@ -142,8 +168,8 @@ HIST_API hist_status hist_findbin(hist_t *h, const void *const *coords, int64_t 
 HIST_API hist_status hist_stats(hist_t *h, double *out, int cap, int *count, void *stream);
 
 /* Bin sums of weights and of squared weights (HOST, T doubles each, either may
- * be NULL) and the entry count (HOST, may be NULL).  Synchronizes `stream`;
- * HIST_ECAPTURE while capturing. */
+ * be NULL) and the entry count (HOST, may be NULL; the device counter of every
+ * fill that has run).  Synchronizes `stream`; HIST_ECAPTURE while capturing. */
 HIST_API hist_status hist_read(hist_t *h, double *sumw, double *sumw2, int64_t *entries, void *stream);
 
 /* Zero bins, statistics and entries.  Asynchronous (fill kernels, no memset). */
@@ -224,14 +250,20 @@ typedef struct {
 
 /* Builds a batch over k handles (distinct, all on this device): a tile list
  * over every member's events and a per-member plan, uploaded once, and a HIP
- * graph that holds one persistent fill launch for all members.  The inputs
- * named in descs are bound into the graph: every hist_batch_launch reads the
- * same device buffers.  Synchronizes.  Errors: HIST_EINVAL, HIST_ENOMEM. */
+ * graph that holds one persistent fill launch for all members (plus the
+ * partition passes of members far larger than LDS; members of more than 2^25
+ * events use global atomics instead).  The batched fill of many histograms
+ * in one launch is the paper's future work (Sec. 6); it is split into this
+ * set-up call and hist_batch_launch so that the set-up (tile lists, plans,
+ * scratch, graph instantiation) is paid once and every launch is one graph
+ * replay.  The inputs named in descs are bound into the graph: every
+ * hist_batch_launch reads the same device buffers.  Allocates and
+ * synchronizes.  Errors: HIST_EINVAL, HIST_ENOMEM, HIST_ECAPTURE. */
 HIST_API hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fill_desc *descs,
                               hist_batch_t **out, void *stream);
 
 /* Replays the batch graph on `stream`: fills every member once (adding to its
- * sums, Sec. 3.3).  Asynchronous. */
+ * sums and entry count, Sec. 3.3).  Asynchronous; allocates nothing. */
 HIST_API hist_status hist_batch_launch(hist_batch_t *b, void *stream);
 
 /* Same work as one replay, launched directly without the graph. */

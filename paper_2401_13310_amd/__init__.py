@@ -12,18 +12,18 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_LEARNED,
+from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_LEARNED, HIST_F_NO_ALLOC,
                    HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED, HIST_STRAT_AUTO, HIST_STRAT_GLOBAL,
                    HIST_STRAT_LDS, HIST_STRAT_PART, HIST_STRAT_TILED, STRAT_NAMES, HistAxis, HistError,
                    HistFillDesc, check, load)
 
 __all__ = [
-    "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_findbin",
+    "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_findbin", "hist_reserve",
     "hist_stats", "hist_read", "hist_reset", "hist_train_index", "hist_set_search",
     "hist_index_info", "hist_set_strategy", "hist_set_window", "hist_tune", "hist_plan_info",
     "hist_timing", "hist_timing_read", "hist_set_threads",
     "hist_batch_create", "hist_batch_launch", "hist_batch_launch_eager", "hist_batch_destroy",
-    "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_STRAT_AUTO",
+    "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_F_NO_ALLOC", "HIST_STRAT_AUTO",
     "HIST_STRAT_LDS", "HIST_STRAT_GLOBAL", "HIST_STRAT_TILED", "HIST_STRAT_PART", "HIST_SEARCH_BINARY",
     "HIST_SEARCH_LEARNED", "Batch",
 ]
@@ -81,6 +81,10 @@ def hist_fill(h, coord_ptrs, weight_ptr, n: int, dtype: int, stream: int) -> Non
 def hist_findbin(h, coord_ptrs, n: int, dtype: int, bins_ptr: int, stream: int) -> None:
     check(load().hist_findbin(h, _col_ptrs(coord_ptrs), n, dtype, bins_ptr, stream),
           "hist_findbin")
+
+
+def hist_reserve(h, n_max: int, dtype: int, weighted: bool, stream: int) -> None:
+    check(load().hist_reserve(h, n_max, dtype, int(bool(weighted)), stream), "hist_reserve")
 
 
 def hist_stats(h, stream: int) -> np.ndarray:
@@ -237,6 +241,9 @@ class Hist:
             raise ValueError("need %d coordinate columns" % self.dims)
         hist_fill(self._h, [c.data_ptr() for c in cols],
                   None if weights is None else weights.data_ptr(), n, dt, _stream_ptr(stream))
+
+    def reserve(self, n_max: int, dtype: int = HIST_F64, weighted: bool = False, stream=None):
+        hist_reserve(self._h, n_max, dtype, weighted, _stream_ptr(stream))
 
     def findbin(self, coords, stream=None):
         import torch

@@ -374,6 +374,10 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
     // and merging of their window.
     constexpr int64_t kPartTile = 65536;          // events per count / scatter tile
     constexpr int64_t kPartMinEvents = 4096;      // fewer events: global atomics
+    // more events: global atomics too -- a partitioned member's slots, bucket
+    // starts and cursors are 32-bit words over all of its events (a single
+    // fill splits such inputs into chunks of the same size instead)
+    constexpr int64_t kPartMaxEvents = (int64_t)1 << 25;
     int max_window_bytes = 0;
     for (int i = 0; i < k; ++i) {
         hist_s *h = hs[i];
@@ -416,6 +420,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         fa.sumw = m.sumw;
         fa.sumw2 = m.sumw2;
         fa.stats = m.stats;
+        fa.entries = h->d_entries;
         fa.lds_win = b->lds_win;
         fa.lds_cache = -1;
         fa.total_bins = (int32_t)h->T;
@@ -434,7 +439,7 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
             fa.win_len = m.win_len;
             fa.copies = m.copies;
             max_window_bytes = std::max(max_window_bytes, (int)(h->T * bytes * m.copies));
-        } else if (part_ok && d.n >= kPartMinEvents) {
+        } else if (part_ok && d.n >= kPartMinEvents && d.n <= kPartMaxEvents) {
             bacc = d.weights ? BA_PCOUNT_W : BA_PCOUNT;
             m.acc = kAccPart;
             m.bshift = pbits;
@@ -610,8 +615,6 @@ extern "C" hist_status hist_batch_launch(hist_batch_t *b, void *stream)
             return set_error(HIST_EDEVICE, "hist_batch_launch: %s", hipGetErrorString(e));
         }
     }
-    for (int i = 0; i < b->k; ++i)
-        b->hs[(size_t)i]->entries += b->n[(size_t)i];
     return HIST_OK;
 }
 
@@ -626,8 +629,6 @@ extern "C" hist_status hist_batch_launch_eager(hist_batch_t *b, void *stream)
             return set_error(HIST_EDEVICE, "hist_batch_launch_eager: %s", hipGetErrorString(e));
         }
     }
-    for (int i = 0; i < b->k; ++i)
-        b->hs[(size_t)i]->entries += b->n[(size_t)i];
     return HIST_OK;
 }
 

@@ -126,6 +126,8 @@ __global__ void __launch_bounds__(kMaxThreads) tiled_bins_kernel(const FillArgs 
 {
     extern __shared__ __align__(16) char smem[];
     constexpr int NS = NStats<D>::v;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && A.entries)
+        gl_add_u64(A.entries, (uint64_t)A.n);
     stage_axes<D>(A.ax, smem);
     __syncthreads();
     double st[NS];

@@ -390,6 +390,9 @@ __device__ __forceinline__ void fill_range(const FillArgs &A, char *smem, int64_
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
 
+    // the fill's entry count, once per fill (the range that starts at event 0)
+    if (start == 0 && tid == 0 && A.entries)
+        gl_add_u64(A.entries, (uint64_t)A.n);
     stage_axes<D>(A.ax, smem);
     uint32_t *win = reinterpret_cast<uint32_t *>(smem + A.lds_win);
     const int words = window_words(ACC, A.win_len, A.copies);

@@ -125,7 +125,8 @@ hist_status hg::zero_state(hist_s *h, hipStream_t s)
     HIPCHK(launch_zero_u64(h->d_cnt, h->T, s), "zero counts");
     HIPCHK(launch_zero_f64(h->d_sumw, h->T, s), "zero sumw");
     HIPCHK(launch_zero_f64(h->d_sumw2, h->T, s), "zero sumw2");
-    HIPCHK(launch_zero_f64(h->d_stats, h->S, s), "zero stats");
+    // statistics and the entry counter (its zero bit pattern) in one launch
+    HIPCHK(launch_zero_f64(h->d_stats, kMaxStats + 2, s), "zero stats");
     return HIST_OK;
 }
 
@@ -140,7 +141,7 @@ extern "C" hist_status hist_create(int dims, const hist_axis *axes, uint32_t fla
         return set_error(HIST_EINVAL, "hist_create: dims must be 1..3 (got %d)", dims);
     if (!axes)
         return set_error(HIST_EINVAL, "hist_create: axes is NULL");
-    if (flags & ~(uint32_t)(HIST_F_ACC_F32C | HIST_F_LEARNED))
+    if (flags & ~(uint32_t)(HIST_F_ACC_F32C | HIST_F_LEARNED | HIST_F_NO_ALLOC))
         return set_error(HIST_EINVAL, "hist_create: unknown flags 0x%x", flags);
     int64_t T = 1;
     for (int a = 0; a < dims; ++a) {
@@ -228,7 +229,9 @@ extern "C" hist_status hist_create(int dims, const hist_axis *axes, uint32_t fla
     if (e == hipSuccess)
         e = dalloc(&h->d_sumw2, (size_t)T);
     if (e == hipSuccess)
-        e = dalloc(&h->d_stats, (size_t)kMaxStats);
+        e = dalloc(&h->d_stats, (size_t)kMaxStats + 2);   // statistics, then the entry count
+    if (e == hipSuccess)
+        h->d_entries = reinterpret_cast<uint64_t *>(h->d_stats + kMaxStats + 1);
     if (e != hipSuccess) {
         free_handle(h);
         return set_error(e == hipErrorOutOfMemory ? HIST_ENOMEM : HIST_EDEVICE,
@@ -270,13 +273,26 @@ extern "C" int hist_nstats(const hist_t *h) { return h ? h->S : -1; }
 
 // ---------------------------------------------------------------- scratch --
 
-hist_status hg::ensure_stage(hist_s *h, size_t bytes, hipStream_t s)
+// A fill may grow its scratch only outside capture and only for handles
+// created without HIST_F_NO_ALLOC; hist_reserve always may.
+static hist_status may_grow(hist_s *h, hipStream_t s, bool reserving, const char *what)
+{
+    if (!reserving && (h->flags & HIST_F_NO_ALLOC))
+        return set_error(HIST_ENOMEM, "hist_fill: the %s this plan needs exceeds what "
+                                      "hist_reserve set aside (HIST_F_NO_ALLOC handle)", what);
+    if (is_capturing(s))
+        return set_error(HIST_ECAPTURE, "hist_fill: the %s this plan needs is not allocated; "
+                                        "call hist_reserve (or fill once) before capturing", what);
+    return HIST_OK;
+}
+
+hist_status hg::ensure_stage(hist_s *h, size_t bytes, hipStream_t s, bool reserving)
 {
     if (h->stage_bytes >= bytes)
         return HIST_OK;
-    if (is_capturing(s))
-        return set_error(HIST_ECAPTURE, "hist_fill: the staging buffer for this plan is not "
-                                        "allocated yet; fill once before capturing");
+    hist_status g = may_grow(h, s, reserving, "staging buffer");
+    if (g != HIST_OK)
+        return g;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess)
@@ -290,13 +306,13 @@ hist_status hg::ensure_stage(hist_s *h, size_t bytes, hipStream_t s)
     return HIST_OK;
 }
 
-hist_status hg::ensure_gbins(hist_s *h, int64_t count, hipStream_t s)
+hist_status hg::ensure_gbins(hist_s *h, int64_t count, hipStream_t s, bool reserving)
 {
     if (h->gbins_cap >= count)
         return HIST_OK;
-    if (is_capturing(s))
-        return set_error(HIST_ECAPTURE, "hist_fill: the tiled-plan scratch is not allocated "
-                                        "yet; fill once before capturing");
+    hist_status g = may_grow(h, s, reserving, "bin scratch");
+    if (g != HIST_OK)
+        return g;
     int32_t *p = nullptr;
     hipError_t e = dalloc(&p, (size_t)count);
     if (e != hipSuccess)
@@ -310,13 +326,13 @@ hist_status hg::ensure_gbins(hist_s *h, int64_t count, hipStream_t s)
     return HIST_OK;
 }
 
-static hist_status ensure_part(hist_s *h, size_t bytes, hipStream_t s)
+static hist_status ensure_part(hist_s *h, size_t bytes, hipStream_t s, bool reserving = false)
 {
     if (h->part_bytes >= bytes)
         return HIST_OK;
-    if (is_capturing(s))
-        return set_error(HIST_ECAPTURE, "hist_fill: the partition scratch is not allocated "
-                                        "yet; fill once before capturing");
+    hist_status g = may_grow(h, s, reserving, "partition scratch");
+    if (g != HIST_OK)
+        return g;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess)
@@ -332,6 +348,27 @@ static hist_status ensure_part(hist_s *h, size_t bytes, hipStream_t s)
     return HIST_OK;
 }
 
+// Scratch layout of the partitioned strategy for chunks of at most mmax
+// events: the count table, four (nbuckets + 1)-word arrays, the in-bucket
+// offsets and (weighted) the weights in bucket order.
+struct PartLayout {
+    int nb;
+    size_t table_b, start_b, off_b, w_b;
+    size_t total() const { return table_b + start_b + off_b + w_b; }
+};
+
+static PartLayout part_layout(const hist_s *h, const Plan &p, int64_t mmax, bool weighted)
+{
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    PartLayout L;
+    L.nb = (int)((h->T + ((int64_t)1 << p.bucket_bits) - 1) >> p.bucket_bits);
+    L.table_b = up((size_t)L.nb * p.blocks * 4);
+    L.start_b = 4 * up((size_t)(L.nb + 1) * 4);
+    L.off_b = up((size_t)mmax * 2);
+    L.w_b = weighted ? up((size_t)mmax * 8) : 0;
+    return L;
+}
+
 // The four passes of the partitioned strategy over chunks of at most
 // part_chunk events (see partition.hip).
 static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *const *coords,
@@ -341,15 +378,14 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
     const int64_t cap = part_chunk(h);
     const int64_t mmax = n < cap ? n : cap;
     const int b = p.bucket_bits;
-    const int nb = (int)((h->T + ((int64_t)1 << b) - 1) >> b);
+    const PartLayout L = part_layout(h, p, mmax, weighted);
+    const int nb = L.nb;
     const int G = p.blocks;
-    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t table_b = up((size_t)nb * G * 4), start_b = 4 * up((size_t)(nb + 1) * 4);
-    const size_t off_b = up((size_t)mmax * 2), w_b = weighted ? up((size_t)mmax * 8) : 0;
+    const size_t table_b = L.table_b, start_b = L.start_b, off_b = L.off_b;
     hist_status st = ensure_gbins(h, mmax, s);
     if (st != HIST_OK)
         return st;
-    st = ensure_part(h, table_b + start_b + off_b + w_b, s);
+    st = ensure_part(h, L.total(), s);
     if (st != HIST_OK)
         return st;
     char *base = static_cast<char *>(h->d_part);
@@ -511,6 +547,7 @@ FillArgs hg::base_args(const hist_s *h, const void *const *coords, const void *w
     a.sumw = h->d_sumw;
     a.sumw2 = h->d_sumw2;
     a.stats = h->d_stats;
+    a.entries = h->d_entries;
     a.stage = h->d_stage;
     return a;
 }
@@ -632,9 +669,38 @@ extern "C" hist_status hist_fill(hist_t *h, const void *const *coords, const voi
         return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     Plan p = make_plan(h, n, dtype, weights != nullptr);
-    st = run_plan(h, p, coords, weights, n, dtype, s);
-    if (st == HIST_OK)
-        h->entries += n;
+    return run_plan(h, p, coords, weights, n, dtype, s);
+}
+
+extern "C" hist_status hist_reserve(hist_t *h, int64_t n_max, hist_dtype dtype, int weighted,
+                                    void *stream)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_reserve: NULL handle");
+    if (n_max < 0 || (dtype != HIST_F64 && dtype != HIST_F32))
+        return set_error(HIST_EINVAL, "hist_reserve: need n_max >= 0 and a known dtype");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (is_capturing(s))
+        return set_error(HIST_ECAPTURE, "hist_reserve: stream is capturing");
+    if (n_max == 0)
+        return HIST_OK;
+    // Under one plan choice the scratch a fill needs grows with n (more
+    // workgroups up to the plan's grid, longer chunks, more buckets), so the
+    // plan of n_max events bounds every smaller fill.
+    const Plan p = make_plan(h, n_max, dtype, weighted != 0);
+    hist_status st = HIST_OK;
+    if (p.strategy == HIST_STRAT_LDS && p.merge == MERGE_STAGE)
+        st = ensure_stage(h, stage_bytes_for(p), s, true);
+    if (st == HIST_OK && p.strategy == HIST_STRAT_TILED)
+        st = ensure_gbins(h, std::min<int64_t>(n_max, tiled_chunk(h)), s, true);
+    if (st == HIST_OK && p.strategy == HIST_STRAT_PART) {
+        const int64_t mmax = std::min<int64_t>(n_max, part_chunk(h));
+        st = ensure_gbins(h, mmax, s, true);
+        if (st == HIST_OK)
+            st = ensure_part(h, part_layout(h, p, mmax, weighted != 0).total(), s, true);
+    }
+    if (st == HIST_OK && hipStreamSynchronize(s) != hipSuccess)
+        st = hip_fail(hipGetLastError(), "hist_reserve: synchronize");
     return st;
 }
 
@@ -712,8 +778,12 @@ extern "C" hist_status hist_read(hist_t *h, double *sumw, double *sumw2, int64_t
     } else {
         HIPCHK(hipStreamSynchronize(s), "read synchronize");
     }
-    if (entries)
-        *entries = h->entries;
+    if (entries) {
+        uint64_t e = 0;
+        HIPCHK(hipMemcpyAsync(&e, h->d_entries, sizeof(e), hipMemcpyDeviceToHost, s), "entries copy");
+        HIPCHK(hipStreamSynchronize(s), "entries synchronize");
+        *entries = (int64_t)e;
+    }
     return HIST_OK;
 }
 
@@ -721,10 +791,7 @@ extern "C" hist_status hist_reset(hist_t *h, void *stream)
 {
     if (!h)
         return set_error(HIST_EINVAL, "hist_reset: NULL handle");
-    hist_status st = zero_state(h, static_cast<hipStream_t>(stream));
-    if (st == HIST_OK)
-        h->entries = 0;
-    return st;
+    return zero_state(h, static_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------- learned index ----

@@ -106,6 +106,7 @@ struct FillArgs {
     uint64_t *cnt;            // [T] unit-weight counts
     double *sumw, *sumw2;     // [T] weighted sums
     double *stats;            // [S]
+    uint64_t *entries;        // entry count: the workgroup that starts at event 0 adds n
     void *stage;              // staging, one slot of stage_stride units per block
     int64_t stage_stride;     // units per block: u32 words (U32/U16) or bins (F64/F32C)
     int32_t *gbins;           // TILED pass 1 / PCOUNT: global bin of every event

@@ -75,7 +75,7 @@ struct hist_s {
     // where they are and how many
     const void *part_zero_at = nullptr;
     int part_zero_n = 0;
-    int64_t entries = 0;
+    uint64_t *d_entries = nullptr;                       // entry count, inside d_stats' allocation
     hg::PlanChoice forced;                               // hist_set_strategy
     // kernel timing (hist_timing): event pairs around the fill and merge kernels
     bool timing = false;
@@ -90,8 +90,8 @@ namespace hg {
 hist_status set_error(hist_status st, const char *fmt, ...);
 uint64_t host_order_key(double x);
 hist_status zero_state(hist_s *h, hipStream_t s);
-hist_status ensure_stage(hist_s *h, size_t bytes, hipStream_t s);
-hist_status ensure_gbins(hist_s *h, int64_t count, hipStream_t s);
+hist_status ensure_stage(hist_s *h, size_t bytes, hipStream_t s, bool reserving = false);
+hist_status ensure_gbins(hist_s *h, int64_t count, hipStream_t s, bool reserving = false);
 FillArgs base_args(const hist_s *h, const void *const *coords, const void *w, int64_t n);
 // Places the learned models of the axes in LDS after the statistics area;
 // returns the first free LDS byte.

@@ -369,24 +369,25 @@ extern "C" hist_status hist_set_window(hist_t *h, int64_t window_lo, int merge)
 
 namespace {
 
+// The histogram's device state: counts, sums, and the statistics with the
+// entry count behind them (kMaxStats + 2 words).
 struct Saved {
     uint64_t *cnt = nullptr;
     double *sumw = nullptr, *sumw2 = nullptr, *stats = nullptr;
-    int64_t entries = 0;
 };
+constexpr size_t kStatsWords = kMaxStats + 2;
 
 hist_status save_state(hist_s *h, Saved &sv, hipStream_t s)
 {
     const size_t T = (size_t)h->T;
     if (hipMalloc(&sv.cnt, T * 8) != hipSuccess || hipMalloc(&sv.sumw, T * 8) != hipSuccess ||
-        hipMalloc(&sv.sumw2, T * 8) != hipSuccess || hipMalloc(&sv.stats, 8 * kMaxStats) != hipSuccess)
+        hipMalloc(&sv.sumw2, T * 8) != hipSuccess || hipMalloc(&sv.stats, 8 * kStatsWords) != hipSuccess)
         return set_error(HIST_ENOMEM, "hist_tune: cannot save the histogram");
     if (hipMemcpyAsync(sv.cnt, h->d_cnt, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
         hipMemcpyAsync(sv.sumw, h->d_sumw, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
         hipMemcpyAsync(sv.sumw2, h->d_sumw2, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(sv.stats, h->d_stats, 8 * kMaxStats, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        hipMemcpyAsync(sv.stats, h->d_stats, 8 * kStatsWords, hipMemcpyDeviceToDevice, s) != hipSuccess)
         return set_error(HIST_EDEVICE, "hist_tune: save copy failed");
-    sv.entries = h->entries;
     return HIST_OK;
 }
 
@@ -397,14 +398,13 @@ hist_status restore_state(hist_s *h, Saved &sv, hipStream_t s)
     if (sv.cnt && (hipMemcpyAsync(h->d_cnt, sv.cnt, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
                    hipMemcpyAsync(h->d_sumw, sv.sumw, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
                    hipMemcpyAsync(h->d_sumw2, sv.sumw2, T * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
-                   hipMemcpyAsync(h->d_stats, sv.stats, 8 * kMaxStats, hipMemcpyDeviceToDevice, s) != hipSuccess))
+                   hipMemcpyAsync(h->d_stats, sv.stats, 8 * kStatsWords, hipMemcpyDeviceToDevice, s) != hipSuccess))
         st = set_error(HIST_EDEVICE, "hist_tune: restore copy failed");
     (void)hipStreamSynchronize(s);
     (void)hipFree(sv.cnt);
     (void)hipFree(sv.sumw);
     (void)hipFree(sv.sumw2);
     (void)hipFree(sv.stats);
-    h->entries = sv.entries;
     return st;
 }
 
