@@ -160,6 +160,37 @@ HIST_API hist_status hist_reserve(hist_t *h, int64_t n_max, hist_dtype dtype, in
 HIST_API hist_status hist_findbin(hist_t *h, const void *const *coords, int64_t n, hist_dtype dtype,
                          int32_t *bins_dev, void *stream);
 
+/* ---- events in host memory -------------------------------------------------- */
+
+/* hist_fill_host flag: the coordinate and weight arrays are page-locked
+ * (hipHostMalloc) and are copied to the device directly. */
+#define HIST_HOST_PINNED  (1u << 0)
+
+/* Fill n events whose columns are in HOST memory, as the paper's histogram
+ * does for every bulk (Sec. 3.2: copy the bulk to the device, then fill), but
+ * pipelined (the overlap Sec. 6 leaves as future work): the events go through
+ * the device in chunks of `chunk` events (0 = 4,194,304) over two slots, so
+ * the host->device copy of one chunk runs on a copy stream of the handle while
+ * the fill of the previous one runs on `stream`.  Pageable input is first
+ * copied by host threads into page-locked staging buffers of the handle;
+ * with HIST_HOST_PINNED the copy engine reads the caller's arrays directly.
+ * A staging buffer or device slot is reused only after the copy or fill that
+ * last used it has run, so a refill never races a copy still reading it (the
+ * host-buffer race of Sec. 3.3).
+ * coords: HOST array of dims HOST pointers to n contiguous values of `dtype`;
+ * weights: HOST pointer or NULL (unit weights).  Same result as hist_fill of
+ * the same events (entries grow by n).
+ * Returns once the caller's arrays have been read completely (they may then
+ * be reused or freed); the fills may still be running on `stream`.
+ * Allocates the slots on first use or growth (page-locked host and device
+ * memory, kept by the handle) and the fill scratch of a chunk; waits on host
+ * for copies of earlier chunks.  HIST_ECAPTURE while `stream` is capturing.
+ * Errors: HIST_EINVAL (n < 0, chunk < 0, NULL pointers, unknown flags),
+ * HIST_ENOMEM, HIST_EDEVICE. */
+HIST_API hist_status hist_fill_host(hist_t *h, const void *const *coords, const void *weights,
+                                    int64_t n, hist_dtype dtype, int64_t chunk, uint32_t flags,
+                                    void *stream);
+
 /* ---- reading (the only synchronizing calls) -------------------------------- */
 
 /* Statistics (layout above) into HOST out[cap]; *count = S.  cap < S:

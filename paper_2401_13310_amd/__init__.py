@@ -13,17 +13,19 @@ import ctypes
 import numpy as np
 
 from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_LEARNED, HIST_F_NO_ALLOC,
-                   HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED, HIST_STRAT_AUTO, HIST_STRAT_GLOBAL,
+                   HIST_HOST_PINNED, HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED, HIST_STRAT_AUTO, HIST_STRAT_GLOBAL,
                    HIST_STRAT_LDS, HIST_STRAT_PART, HIST_STRAT_TILED, STRAT_NAMES, HistAxis, HistError,
                    HistFillDesc, check, load)
 
 __all__ = [
-    "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_findbin", "hist_reserve",
+    "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_fill_host", "hist_findbin",
+    "hist_reserve",
     "hist_stats", "hist_read", "hist_reset", "hist_train_index", "hist_set_search",
     "hist_index_info", "hist_set_strategy", "hist_set_window", "hist_tune", "hist_plan_info",
     "hist_timing", "hist_timing_read", "hist_set_threads",
     "hist_batch_create", "hist_batch_launch", "hist_batch_launch_eager", "hist_batch_destroy",
-    "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_F_NO_ALLOC", "HIST_STRAT_AUTO",
+    "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_F_NO_ALLOC", "HIST_HOST_PINNED",
+    "HIST_STRAT_AUTO",
     "HIST_STRAT_LDS", "HIST_STRAT_GLOBAL", "HIST_STRAT_TILED", "HIST_STRAT_PART", "HIST_SEARCH_BINARY",
     "HIST_SEARCH_LEARNED", "Batch",
 ]
@@ -76,6 +78,12 @@ def hist_destroy(h) -> None:
 
 def hist_fill(h, coord_ptrs, weight_ptr, n: int, dtype: int, stream: int) -> None:
     check(load().hist_fill(h, _col_ptrs(coord_ptrs), weight_ptr, n, dtype, stream), "hist_fill")
+
+
+def hist_fill_host(h, coord_ptrs, weight_ptr, n: int, dtype: int, chunk: int, flags: int,
+                   stream: int) -> None:
+    check(load().hist_fill_host(h, _col_ptrs(coord_ptrs), weight_ptr, n, dtype, chunk, flags, stream),
+          "hist_fill_host")
 
 
 def hist_findbin(h, coord_ptrs, n: int, dtype: int, bins_ptr: int, stream: int) -> None:
@@ -241,6 +249,29 @@ class Hist:
             raise ValueError("need %d coordinate columns" % self.dims)
         hist_fill(self._h, [c.data_ptr() for c in cols],
                   None if weights is None else weights.data_ptr(), n, dt, _stream_ptr(stream))
+
+    def fill_host(self, coords, weights=None, chunk: int = 0, pinned: bool = False, stream=None):
+        """Fill from host columns (numpy arrays or CPU tensors, one dtype,
+        contiguous); pinned=True for page-locked tensors (pin_memory)."""
+        import torch
+        cols = [torch.as_tensor(c) for c in coords]
+        if len(cols) != self.dims:
+            raise ValueError("need %d coordinate columns" % self.dims)
+        w = None if weights is None else torch.as_tensor(weights)
+        dt = cols[0].dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("coordinates must be float64 or float32")
+        n = cols[0].numel()
+        for c in cols + ([w] if w is not None else []):
+            if c.is_cuda:
+                raise ValueError("fill_host takes host columns")
+            if c.dtype != dt or not c.is_contiguous() or c.dim() != 1 or c.numel() != n:
+                raise ValueError("columns must be contiguous 1-D arrays of one dtype and length")
+            if pinned and not c.is_pinned():
+                raise ValueError("pinned=True needs page-locked tensors")
+        hist_fill_host(self._h, [c.data_ptr() for c in cols], None if w is None else w.data_ptr(), n,
+                       HIST_F32 if dt == torch.float32 else HIST_F64, chunk,
+                       HIST_HOST_PINNED if pinned else 0, _stream_ptr(stream))
 
     def reserve(self, n_max: int, dtype: int = HIST_F64, weighted: bool = False, stream=None):
         hist_reserve(self._h, n_max, dtype, weighted, _stream_ptr(stream))

@@ -19,6 +19,7 @@ HIST_F64, HIST_F32 = 0, 1
 HIST_F_ACC_F32C = 1 << 0
 HIST_F_LEARNED = 1 << 1
 HIST_F_NO_ALLOC = 1 << 2
+HIST_HOST_PINNED = 1 << 0
 HIST_STRAT_AUTO, HIST_STRAT_LDS, HIST_STRAT_GLOBAL, HIST_STRAT_TILED, HIST_STRAT_PART = range(5)
 HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED = 0, 1
 ACC_NAMES = {0: "u32", 1: "u16", 2: "f64", 3: "f32c"}
@@ -47,6 +48,8 @@ PROTOTYPES = {
                           ctypes.POINTER(_H)]),
     "hist_destroy": (_st, [_H]),
     "hist_fill": (_st, [_H, ctypes.POINTER(_P), _P, ctypes.c_int64, ctypes.c_int, _P]),
+    "hist_fill_host": (_st, [_H, ctypes.POINTER(_P), _P, ctypes.c_int64, ctypes.c_int,
+                             ctypes.c_int64, ctypes.c_uint32, _P]),
     "hist_findbin": (_st, [_H, ctypes.POINTER(_P), ctypes.c_int64, ctypes.c_int, _P, _P]),
     "hist_reserve": (_st, [_H, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _P]),
     "hist_stats": (_st, [_H, ctypes.POINTER(ctypes.c_double), ctypes.c_int,

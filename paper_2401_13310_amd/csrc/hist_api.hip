@@ -117,6 +117,7 @@ static void free_handle(hist_s *h)
     dfree(h->d_part);
     for (hipEvent_t e : h->ev_pool)
         (void)hipEventDestroy(e);
+    host_streamer_destroy(h->host);
     delete h;
 }
 
@@ -684,10 +685,19 @@ extern "C" hist_status hist_reserve(hist_t *h, int64_t n_max, hist_dtype dtype, 
         return set_error(HIST_ECAPTURE, "hist_reserve: stream is capturing");
     if (n_max == 0)
         return HIST_OK;
+    hist_status st = reserve_scratch(h, n_max, dtype, weighted != 0, s);
+    if (st == HIST_OK && hipStreamSynchronize(s) != hipSuccess)
+        st = hip_fail(hipGetLastError(), "hist_reserve: synchronize");
+    return st;
+}
+
+hist_status hg::reserve_scratch(hist_s *h, int64_t n_max, hist_dtype dtype, bool weighted,
+                                hipStream_t s)
+{
     // Under one plan choice the scratch a fill needs grows with n (more
     // workgroups up to the plan's grid, longer chunks, more buckets), so the
     // plan of n_max events bounds every smaller fill.
-    const Plan p = make_plan(h, n_max, dtype, weighted != 0);
+    const Plan p = make_plan(h, n_max, dtype, weighted);
     hist_status st = HIST_OK;
     if (p.strategy == HIST_STRAT_LDS && p.merge == MERGE_STAGE)
         st = ensure_stage(h, stage_bytes_for(p), s, true);
@@ -697,10 +707,8 @@ extern "C" hist_status hist_reserve(hist_t *h, int64_t n_max, hist_dtype dtype, 
         const int64_t mmax = std::min<int64_t>(n_max, part_chunk(h));
         st = ensure_gbins(h, mmax, s, true);
         if (st == HIST_OK)
-            st = ensure_part(h, part_layout(h, p, mmax, weighted != 0).total(), s, true);
+            st = ensure_part(h, part_layout(h, p, mmax, weighted).total(), s, true);
     }
-    if (st == HIST_OK && hipStreamSynchronize(s) != hipSuccess)
-        st = hip_fail(hipGetLastError(), "hist_reserve: synchronize");
     return st;
 }
 

@@ -12,6 +12,11 @@
 namespace hg {
 
 constexpr int kMaxSegments = 1024;
+// Events per chunk of hist_fill_host when the caller passes 0.
+constexpr int64_t kHostChunkDefault = (int64_t)1 << 22;
+
+struct HostStreamer;
+void host_streamer_destroy(HostStreamer *hs);
 
 // How one fill is launched.
 struct Plan {
@@ -83,6 +88,7 @@ struct hist_s {
     std::vector<std::pair<int, int>> ev_fill, ev_merge;  // indices into ev_pool
     int ev_next = 0;
     std::map<std::tuple<int, int, int>, hg::PlanChoice> tuned;  // (acc, f32, n bucket)
+    hg::HostStreamer *host = nullptr;                    // hist_fill_host buffers and copy stream
 };
 
 namespace hg {
@@ -92,6 +98,9 @@ uint64_t host_order_key(double x);
 hist_status zero_state(hist_s *h, hipStream_t s);
 hist_status ensure_stage(hist_s *h, size_t bytes, hipStream_t s, bool reserving = false);
 hist_status ensure_gbins(hist_s *h, int64_t count, hipStream_t s, bool reserving = false);
+// The scratch of the plan for fills of up to n_max events (hist_reserve
+// without its synchronization).
+hist_status reserve_scratch(hist_s *h, int64_t n_max, hist_dtype dtype, bool weighted, hipStream_t s);
 FillArgs base_args(const hist_s *h, const void *const *coords, const void *w, int64_t n);
 // Places the learned models of the axes in LDS after the statistics area;
 // returns the first free LDS byte.
