@@ -53,6 +53,7 @@ extern "C" {
 
 typedef struct hist_s hist_t;
 typedef struct hist_batch_s hist_batch_t;
+typedef struct hist_multi_s hist_multi_t;
 
 typedef enum {
     HIST_OK = 0,
@@ -301,6 +302,85 @@ HIST_API hist_status hist_batch_launch(hist_batch_t *b, void *stream);
 HIST_API hist_status hist_batch_launch_eager(hist_batch_t *b, void *stream);
 
 HIST_API hist_status hist_batch_destroy(hist_batch_t *b);
+
+/* ---- event filters, computed columns, several histograms per pass ----------- */
+
+/* Operations of the postfix programs of hist_define.  Values are binary64
+ * (FP32 columns are widened exactly); every operation is exactly rounded
+ * (IEEE 754), no contraction into fused multiply-adds, so results are
+ * bit-reproducible.  Comparisons and logic give 1.0 or 0.0; a value is true
+ * when it is nonzero (NaN is true).
+ *   COL c: push column c          CONST v: push v
+ *   NEG ABS SQRT NOT: replace the top value a by -a, |a|, sqrt(a), (a == 0)
+ *   ADD SUB MUL DIV: a op b of the two top values (b on top)
+ *   MIN: (b < a ? b : a)    MAX: (a < b ? b : a)
+ *   LT LE GT GE EQ NE: a op b       AND OR: logical of (a != 0), (b != 0)
+ *   SELECT: c a b -> (c != 0 ? a : b) */
+typedef enum {
+    HIST_OP_COL = 0, HIST_OP_CONST = 1, HIST_OP_ADD = 2, HIST_OP_SUB = 3, HIST_OP_MUL = 4,
+    HIST_OP_DIV = 5, HIST_OP_NEG = 6, HIST_OP_ABS = 7, HIST_OP_SQRT = 8, HIST_OP_MIN = 9,
+    HIST_OP_MAX = 10, HIST_OP_LT = 11, HIST_OP_LE = 12, HIST_OP_GT = 13, HIST_OP_GE = 14,
+    HIST_OP_EQ = 15, HIST_OP_NE = 16, HIST_OP_AND = 17, HIST_OP_OR = 18, HIST_OP_NOT = 19,
+    HIST_OP_SELECT = 20
+} hist_opcode;
+
+typedef struct {
+    int32_t op;      /* hist_opcode */
+    int32_t col;     /* HIST_OP_COL: column index */
+    double value;    /* HIST_OP_CONST */
+} hist_op;
+
+/* A postfix program of 1..32 operations leaving one value, stack depth at
+ * most 6; nops == 0 means absent. */
+typedef struct {
+    const hist_op *ops;
+    int32_t nops;
+} hist_expr;
+
+/* What one histogram takes from the shared columns: the Filter and Define
+ * steps in front of a histogram fill in the paper's RDataFrame usage (Sec. 3,
+ * Listing 1; its CUDA kernel skips events marked invalid, Sec. 3.2).
+ *   filter:   the event is filled only where the program is nonzero; a
+ *             filtered-out event changes nothing (no bin, statistics or
+ *             entry).  Absent: every event.
+ *   coord[a]: the coordinate on axis a.  Absent: column a.
+ *   weight:   the event weight.  Absent: unit weight. */
+typedef struct {
+    hist_expr filter;
+    hist_expr coord[3];
+    hist_expr weight;
+} hist_define;
+
+/* Prepares one pass that fills k (1..16) distinct histograms (all on this
+ * device) from ncols (1..8) shared columns of `dtype`: the paper's future
+ * work of several histograms per event loop (Sec. 6).  defs[k] (NULL: every
+ * member takes columns 0..dims-1 as coordinates, unit weights, no filter).
+ * Programs are checked here (operations, column indices, stack depth).  The
+ * plan keeps each member's statistics, learned models and edge arrays of at
+ * most 4,096 edges in LDS, then whole-histogram copies of the smallest members
+ * while LDS lasts; other members take global atomics.  Handles must outlive
+ * the plan; they may still be filled on their own.  Allocates and copies the
+ * plan to the device (synchronous).  Errors: HIST_EINVAL, HIST_ENOMEM,
+ * HIST_EDEVICE. */
+HIST_API hist_status hist_multi_create(int k, hist_t *const *hs, const hist_define *defs, int ncols,
+                                       hist_dtype dtype, hist_multi_t **out);
+
+/* One pass over n events: columns is a HOST array of ncols DEVICE pointers
+ * to n contiguous values each.  Every member adds the events its filter keeps
+ * (bins, statistics, entries), as hist_fill of its defined coordinates and
+ * weights would.  Asynchronous on `stream`; allocates nothing (capture-safe).
+ * Errors: HIST_EINVAL (NULL plan or column, n < 0), HIST_EDEVICE. */
+HIST_API hist_status hist_multi_fill(hist_multi_t *m, const void *const *columns, int64_t n,
+                                     void *stream);
+
+/* Where member `member` accumulates: in_lds = 1 for an LDS copy (with
+ * `copies` interleaved copies), 0 for global atomics; lds_bytes = dynamic LDS
+ * of the pass. */
+HIST_API hist_status hist_multi_info(const hist_multi_t *m, int member, int *in_lds, int *copies,
+                                     int *lds_bytes);
+
+/* Frees the plan (synchronizes the device).  NULL is accepted. */
+HIST_API hist_status hist_multi_destroy(hist_multi_t *m);
 
 /* ---- introspection -------------------------------------------------------- */
 

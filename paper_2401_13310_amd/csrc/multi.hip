@@ -1,0 +1,769 @@
+// multi.hip -- one pass over shared event columns that fills several
+// histograms, each behind its own event filter and computed columns.
+//
+// The paper fills one histogram per pass and names several histograms per
+// event loop as future work (arXiv:2401.13310 Sec. 6).  Its RDataFrame usage
+// (Sec. 3, Listing 1) puts a Filter and a Define in front of the histogram
+// fill, and its CUDA kernel skips events whose bin was marked invalid
+// (Sec. 3.2).  Here the columns of a batch of events are read from HBM once;
+// for every member histogram the kernel then evaluates the member's filter,
+// coordinate and weight programs on those values, finds the bins (Sec. 3.1)
+// and accumulates into the member's private LDS copy (Sec. 3.2 two-stage
+// fill) or, for a member too large for the LDS left, with global atomics.
+// Statistics sums and entry counts are kept per member; filtered-out events
+// count nowhere.
+//
+// Programs are postfix expressions over binary64 values (hist.h lists the
+// operations).  The stack depth before every operation is fixed by the
+// program, so the host stores it with the operation and the kernel dispatches
+// on (depth, operation): every stack slot is then a register named at compile
+// time.  Programs and depths are the same for every lane, so the dispatch is
+// scalar branching, paid once per batch of events.
+#include "../../include/hist.h"
+#include "device_common.h"
+#include "kernels.h"
+#include "plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+namespace hg {
+
+constexpr int kMultiMembers = 16;
+constexpr int kMultiCols = 8;
+constexpr int kExprStack = 6;
+constexpr int kExprMaxOps = 32;
+constexpr int kMultiU = 2;           // events per thread per batch
+constexpr int kMultiStatsBytes = 96; // per member: kMaxStats doubles, then the kept count
+
+struct ExprOp {
+    int32_t code;    // hist_opcode
+    int32_t sp;      // stack depth before the operation
+    int32_t col;     // HIST_OP_COL: column index
+    int32_t pad;
+    double value;    // HIST_OP_CONST
+};
+
+struct ExprRef {
+    int32_t first;   // index of the first operation
+    int32_t nops;    // 0: absent
+};
+
+struct MultiMember {
+    AxisDev ax[kMaxDims];
+    int32_t dims;
+    int32_t nstats;
+    int32_t lds_win;      // byte offset of the LDS copy of the histogram, -1: global atomics
+    int32_t copies;       // interleaved copies in that LDS region
+    int32_t lds_stats;    // byte offset of the statistics partials and kept count
+    int32_t total_bins;
+    ExprRef filter, coord[kMaxDims], weight;
+    uint64_t *cnt;
+    double *sumw, *sumw2, *stats;
+    uint64_t *entries;
+};
+
+// Members and operations are read through the constant address space: every
+// field is then a scalar load (the values are the same for every lane).
+using ConstMultiMember = __attribute__((address_space(4))) const MultiMember;
+using ConstExprOp = __attribute__((address_space(4))) const ExprOp;
+
+struct MultiArgs {
+    const MultiMember *members;
+    const ExprOp *ops;
+    const void *cols[kMultiCols];
+    int32_t k;
+    int32_t ncols;
+    int64_t n;
+    int64_t per_block;
+};
+
+// ---------------------------------------------------------------- programs --
+
+__device__ __forceinline__ double truth(bool b) { return b ? 1.0 : 0.0; }
+
+// One operation at stack depth SP on U events.  Binary operations take the
+// two top slots and leave the result in the lower one; SELECT (c, a, b) keeps
+// a where c is nonzero, else b.
+template <int SP, int NC, int U>
+__device__ __forceinline__ void expr_step(const ExprOp &op, double (&r)[kExprStack][U],
+                                          const double (&cv)[NC][U])
+{
+#pragma clang fp contract(off)
+    const int code = op.code;
+    if (code == HIST_OP_COL || code == HIST_OP_CONST) {
+        if constexpr (SP < kExprStack) {
+            if (code == HIST_OP_CONST) {
+#pragma unroll
+                for (int j = 0; j < U; ++j)
+                    r[SP][j] = op.value;
+            } else {
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    if (op.col == c) {
+#pragma unroll
+                        for (int j = 0; j < U; ++j)
+                            r[SP][j] = cv[c][j];
+                    }
+            }
+        }
+        return;
+    }
+    if (code == HIST_OP_NEG || code == HIST_OP_ABS || code == HIST_OP_SQRT || code == HIST_OP_NOT) {
+        if constexpr (SP >= 1) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const double a = r[SP - 1][j];
+                r[SP - 1][j] = code == HIST_OP_NEG   ? -a
+                               : code == HIST_OP_ABS ? __builtin_fabs(a)
+                               : code == HIST_OP_NOT ? truth(a == 0.0)
+                                                     : __builtin_sqrt(a);
+            }
+        }
+        return;
+    }
+    if (code == HIST_OP_SELECT) {
+        if constexpr (SP >= 3) {
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                r[SP - 3][j] = r[SP - 3][j] != 0.0 ? r[SP - 2][j] : r[SP - 1][j];
+        }
+        return;
+    }
+    if constexpr (SP >= 2) {
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const double a = r[SP - 2][j], b = r[SP - 1][j];
+            double v;
+            switch (code) {
+            case HIST_OP_ADD: v = a + b; break;
+            case HIST_OP_SUB: v = a - b; break;
+            case HIST_OP_MUL: v = a * b; break;
+            case HIST_OP_DIV: v = a / b; break;
+            case HIST_OP_MIN: v = b < a ? b : a; break;
+            case HIST_OP_MAX: v = a < b ? b : a; break;
+            case HIST_OP_LT: v = truth(a < b); break;
+            case HIST_OP_LE: v = truth(a <= b); break;
+            case HIST_OP_GT: v = truth(a > b); break;
+            case HIST_OP_GE: v = truth(a >= b); break;
+            case HIST_OP_EQ: v = truth(a == b); break;
+            case HIST_OP_NE: v = truth(a != b); break;
+            case HIST_OP_AND: v = truth(a != 0.0 && b != 0.0); break;
+            default: v = truth(a != 0.0 || b != 0.0); break;   // HIST_OP_OR
+            }
+            r[SP - 2][j] = v;
+        }
+    }
+}
+
+// Runs a program on U events; the result is the bottom stack slot.  `r` is
+// the caller's register stack (initialized once, reused by every program).
+template <int NC, int U>
+__device__ __forceinline__ void run_expr(ConstExprOp *ops, ExprRef e, double (&r)[kExprStack][U],
+                                         const double (&cv)[NC][U], double (&out)[U])
+{
+    for (int pc = 0; pc < e.nops; ++pc) {
+        const ExprOp op = *(const ExprOp *)&ops[e.first + pc];
+        switch (op.sp) {
+        case 0: expr_step<0, NC, U>(op, r, cv); break;
+        case 1: expr_step<1, NC, U>(op, r, cv); break;
+        case 2: expr_step<2, NC, U>(op, r, cv); break;
+        case 3: expr_step<3, NC, U>(op, r, cv); break;
+        case 4: expr_step<4, NC, U>(op, r, cv); break;
+        case 5: expr_step<5, NC, U>(op, r, cv); break;
+        default: expr_step<6, NC, U>(op, r, cv); break;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        out[j] = r[0][j];
+}
+
+// ------------------------------------------------------------------ kernel --
+
+// Bins of U coordinates on one axis of a member: the fixed-width formula, or
+// a binary search over the edges (staged in LDS when the plan put them
+// there).  Learned indexes are not used in these passes: the plan turns such
+// axes into binary-search axes, which keeps the per-member code small.
+template <int U>
+__device__ __forceinline__ void member_axis_bins(const double (&x)[U], const AxisDev &ax,
+                                                 const char *smem, int32_t (&b)[U], bool (&inr)[U])
+{
+    if (ax.kind == AX_UNIFORM) {
+        bins_uniform<U>(x, ax, b, inr);
+        return;
+    }
+    int32_t lo[U], hi[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) {
+        const bool under = x[j] < ax.xmin;
+        inr[j] = !under && x[j] < ax.xmax;
+        const int32_t flow = under ? 0 : ax.nbins + 1;
+        lo[j] = inr[j] ? 1 : flow;
+        hi[j] = inr[j] ? ax.nbins : flow;
+    }
+    if (ax.lds_edges >= 0)
+        search_lockstep<U>(x, lds_edge_ptr(smem, ax), ax.nbins, lo, hi);
+    else
+        search_lockstep<U>(x, ax.edges, ax.nbins, lo, hi);
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        b[j] = lo[j];
+}
+
+template <typename T>
+__device__ __forceinline__ double load_col(const void *p, int64_t i)
+{
+    return (double)__builtin_nontemporal_load(static_cast<const T *>(p) + i);
+}
+
+// Wave sum of a double, then one LDS atomic by the wave's first lane.
+__device__ __forceinline__ void wave_add_lds(double v, double *dst)
+{
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0 && v != 0.0)
+        lds_add_f64(dst, v);
+}
+
+// NC: columns held in registers (at least the plan's ncols).
+template <typename T, int NC>
+__global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs A)
+{
+    constexpr int U = kMultiU;
+    extern __shared__ __align__(16) char smem[];
+    ConstMultiMember *mem = (ConstMultiMember *)A.members;
+    ConstExprOp *ops = (ConstExprOp *)A.ops;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+
+    // stage small edge arrays, zero the statistics and windows
+    for (int m = 0; m < A.k; ++m) {
+        const MultiMember &M = *(const MultiMember *)&mem[m];
+        for (int a = 0; a < M.dims; ++a) {
+            const AxisDev &ax = M.ax[a];
+            if (ax.kind != AX_UNIFORM && ax.lds_edges >= 0) {
+                double *dst = reinterpret_cast<double *>(smem + ax.lds_edges);
+                for (int i = tid; i <= ax.nbins; i += nthr)
+                    dst[i] = ax.edges[i];
+            }
+        }
+        uint32_t *st = reinterpret_cast<uint32_t *>(smem + M.lds_stats);
+        for (int i = tid; i < kMultiStatsBytes / 4; i += nthr)
+            st[i] = 0u;
+        if (M.lds_win >= 0) {
+            uint32_t *win = reinterpret_cast<uint32_t *>(smem + M.lds_win);
+            const int words = M.total_bins * M.copies * (M.weight.nops > 0 ? 4 : 1);
+            for (int i = tid; i < words; i += nthr)
+                win[i] = 0u;
+        }
+    }
+    __syncthreads();
+
+    const int64_t start = (int64_t)blockIdx.x * A.per_block;
+    const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
+    double r[kExprStack][U];
+#pragma unroll
+    for (int s = 0; s < kExprStack; ++s)
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            r[s][j] = 0.0;
+
+    for (int64_t base = start; base < end; base += (int64_t)nthr * U) {
+        double cv[NC][U];
+        bool ok[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            ok[j] = base + (int64_t)j * nthr + tid < end;
+        // every column of the batch is read once, for all members
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int64_t i = base + (int64_t)j * nthr + tid;
+                cv[c][j] = (c < A.ncols && ok[j]) ? load_col<T>(A.cols[c], i) : 0.0;
+            }
+        }
+        for (int m = 0; m < A.k; ++m) {
+            const MultiMember &M = *(const MultiMember *)&mem[m];
+            bool keep[U];
+            {
+                double f[U];
+                if (M.filter.nops > 0) {
+                    run_expr<NC, U>(ops, M.filter, r, cv, f);
+#pragma unroll
+                    for (int j = 0; j < U; ++j)
+                        keep[j] = ok[j] && f[j] != 0.0;
+                } else {
+#pragma unroll
+                    for (int j = 0; j < U; ++j)
+                        keep[j] = ok[j];
+                }
+            }
+            double x[kMaxDims][U];
+#pragma unroll
+            for (int a = 0; a < kMaxDims; ++a) {
+                if (a < M.dims && M.coord[a].nops > 0) {
+                    run_expr<NC, U>(ops, M.coord[a], r, cv, x[a]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < U; ++j)
+                        x[a][j] = a < NC ? cv[a < NC ? a : 0][j] : 0.0;
+                }
+            }
+            const bool weighted = M.weight.nops > 0;
+            double w[U];
+            if (weighted) {
+                run_expr<NC, U>(ops, M.weight, r, cv, w);
+            } else {
+#pragma unroll
+                for (int j = 0; j < U; ++j)
+                    w[j] = 1.0;
+            }
+            // bins on every axis of the member (kinds are uniform)
+            int32_t g[U];
+            bool inside[U];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                g[j] = 0;
+                inside[j] = true;
+            }
+#pragma unroll
+            for (int a = 0; a < kMaxDims; ++a) {
+                if (a < M.dims) {
+                    int32_t b[U];
+                    bool inr[U];
+                    member_axis_bins<U>(x[a], M.ax[a], smem, b, inr);
+#pragma unroll
+                    for (int j = 0; j < U; ++j) {
+                        g[j] += a == 0 ? b[j] : b[j] * M.ax[a].stride;
+                        inside[j] = inside[j] && inr[j];
+                    }
+                }
+            }
+            // accumulate
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                if (!keep[j])
+                    continue;
+                if (M.lds_win >= 0) {
+                    const uint32_t idx = (uint32_t)g[j] * (uint32_t)M.copies + (uint32_t)(tid % M.copies);
+                    if (weighted) {
+                        double *s = reinterpret_cast<double *>(smem + M.lds_win);
+                        lds_add_f64(&s[idx], w[j]);
+                        lds_add_f64(&s[(uint32_t)M.total_bins * M.copies + idx], w[j] * w[j]);
+                    } else {
+                        lds_add_u32(reinterpret_cast<uint32_t *>(smem + M.lds_win) + idx, 1u);
+                    }
+                } else if (weighted) {
+                    gl_add_f64(&M.sumw[g[j]], w[j]);
+                    gl_add_f64(&M.sumw2[g[j]], w[j] * w[j]);
+                } else {
+                    gl_add_u64(&M.cnt[g[j]], 1ull);
+                }
+            }
+            // statistics of the kept in-range events, reduced per wave into LDS
+            double st[kMaxStats];
+#pragma unroll
+            for (int s = 0; s < kMaxStats; ++s)
+                st[s] = 0.0;
+            uint32_t kept = 0;
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                kept += keep[j] ? 1u : 0u;
+                const bool take = keep[j] && inside[j];
+                double xm[kMaxDims];
+#pragma unroll
+                for (int a = 0; a < kMaxDims; ++a)
+                    xm[a] = take ? x[a][j] : 0.0;
+                stats_add_rt(st, xm, take ? w[j] : 0.0, M.dims);
+            }
+            double *lst = reinterpret_cast<double *>(smem + M.lds_stats);
+#pragma unroll
+            for (int s = 0; s < kMaxStats; ++s)
+                if (s < M.nstats)
+                    wave_add_lds(st[s], &lst[s]);
+            {
+                uint32_t v = kept;
+#pragma unroll
+                for (int off = kWave / 2; off > 0; off >>= 1)
+                    v += __shfl_xor(v, off, kWave);
+                if ((tid & (kWave - 1)) == 0 && v)
+                    lds_add_u32(reinterpret_cast<uint32_t *>(lst + kMaxStats), v);
+            }
+        }
+    }
+    __syncthreads();
+
+    // merge: LDS copies into the member histograms, statistics, kept counts
+    for (int m = 0; m < A.k; ++m) {
+        const MultiMember &M = *(const MultiMember *)&mem[m];
+        const bool weighted = M.weight.nops > 0;
+        if (M.lds_win >= 0) {
+            const int C = M.copies;
+            if (weighted) {
+                const double *s = reinterpret_cast<const double *>(smem + M.lds_win);
+                const int n1 = M.total_bins * C;
+                for (int l = tid; l < M.total_bins; l += nthr) {
+                    double a = 0.0, b = 0.0;
+                    for (int c = 0; c < C; ++c) {
+                        a += s[l * C + c];
+                        b += s[n1 + l * C + c];
+                    }
+                    if (a != 0.0 || b != 0.0) {
+                        gl_add_f64(&M.sumw[l], a);
+                        gl_add_f64(&M.sumw2[l], b);
+                    }
+                }
+            } else {
+                const uint32_t *s = reinterpret_cast<const uint32_t *>(smem + M.lds_win);
+                for (int l = tid; l < M.total_bins; l += nthr) {
+                    uint32_t a = 0;
+                    for (int c = 0; c < C; ++c)
+                        a += s[l * C + c];
+                    if (a)
+                        gl_add_u64(&M.cnt[l], a);
+                }
+            }
+        }
+        const double *lst = reinterpret_cast<const double *>(smem + M.lds_stats);
+        if (tid < M.nstats && lst[tid] != 0.0)
+            gl_add_f64(&M.stats[tid], lst[tid]);
+        if (tid == nthr - 1) {
+            const uint32_t kept = *reinterpret_cast<const uint32_t *>(lst + kMaxStats);
+            if (kept)
+                gl_add_u64(M.entries, kept);
+        }
+    }
+}
+
+}  // namespace hg
+
+// -------------------------------------------------------------------- host --
+
+using namespace hg;
+
+struct hist_multi_s {
+    int k = 0;
+    int ncols = 0;
+    hist_dtype dtype = HIST_F64;
+    int device = 0;
+    int num_cu = 256;
+    int lds = 0;
+    MultiMember *d_members = nullptr;
+    ExprOp *d_ops = nullptr;
+    std::vector<MultiMember> members;
+    std::vector<int> window_members;   // indices of members accumulated in LDS
+};
+
+// Checks a postfix program and records the stack depth before each operation.
+static hist_status compile_expr(const hist_expr &e, int ncols, const char *what, int m,
+                                std::vector<ExprOp> &out, ExprRef &ref)
+{
+    ref.first = (int32_t)out.size();
+    ref.nops = 0;
+    if (e.nops == 0)
+        return HIST_OK;
+    if (e.nops < 0 || e.nops > kExprMaxOps || !e.ops)
+        return set_error(HIST_EINVAL, "hist_multi_create: member %d %s: need 1..%d operations", m, what,
+                         kExprMaxOps);
+    int sp = 0;
+    for (int i = 0; i < e.nops; ++i) {
+        const hist_op &o = e.ops[i];
+        int pop, push = 1;
+        switch (o.op) {
+        case HIST_OP_COL:
+            if (o.col < 0 || o.col >= ncols)
+                return set_error(HIST_EINVAL, "hist_multi_create: member %d %s: column %d of %d", m,
+                                 what, o.col, ncols);
+            pop = 0;
+            break;
+        case HIST_OP_CONST: pop = 0; break;
+        case HIST_OP_NEG: case HIST_OP_ABS: case HIST_OP_SQRT: case HIST_OP_NOT: pop = 1; break;
+        case HIST_OP_SELECT: pop = 3; break;
+        case HIST_OP_ADD: case HIST_OP_SUB: case HIST_OP_MUL: case HIST_OP_DIV: case HIST_OP_MIN:
+        case HIST_OP_MAX: case HIST_OP_LT: case HIST_OP_LE: case HIST_OP_GT: case HIST_OP_GE:
+        case HIST_OP_EQ: case HIST_OP_NE: case HIST_OP_AND: case HIST_OP_OR: pop = 2; break;
+        default:
+            return set_error(HIST_EINVAL, "hist_multi_create: member %d %s: unknown operation %d", m,
+                             what, o.op);
+        }
+        if (sp < pop)
+            return set_error(HIST_EINVAL, "hist_multi_create: member %d %s: operation %d needs %d "
+                                          "operands, stack holds %d", m, what, i, pop, sp);
+        if (sp - pop + push > kExprStack)
+            return set_error(HIST_EINVAL, "hist_multi_create: member %d %s: stack deeper than %d", m,
+                             what, kExprStack);
+        ExprOp d;
+        d.code = o.op;
+        d.sp = sp;
+        d.col = o.op == HIST_OP_COL ? o.col : 0;
+        d.pad = 0;
+        d.value = o.op == HIST_OP_CONST ? o.value : 0.0;
+        out.push_back(d);
+        sp = sp - pop + push;
+    }
+    if (sp != 1)
+        return set_error(HIST_EINVAL, "hist_multi_create: member %d %s: program leaves %d values, "
+                                      "needs exactly 1", m, what, sp);
+    ref.nops = e.nops;
+    return HIST_OK;
+}
+
+static void free_multi(hist_multi_s *m)
+{
+    if (!m)
+        return;
+    if (m->d_members)
+        (void)hipFree(m->d_members);
+    if (m->d_ops)
+        (void)hipFree(m->d_ops);
+    (void)hipGetLastError();
+    delete m;
+}
+
+extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_define *defs,
+                                         int ncols, hist_dtype dtype, hist_multi_t **out)
+{
+    if (!out)
+        return set_error(HIST_EINVAL, "hist_multi_create: out is NULL");
+    *out = nullptr;
+    if (k < 1 || k > kMultiMembers || !hs)
+        return set_error(HIST_EINVAL, "hist_multi_create: need 1..%d handles", kMultiMembers);
+    if (ncols < 1 || ncols > kMultiCols)
+        return set_error(HIST_EINVAL, "hist_multi_create: ncols must be 1..%d", kMultiCols);
+    if (dtype != HIST_F64 && dtype != HIST_F32)
+        return set_error(HIST_EINVAL, "hist_multi_create: unknown dtype %d", (int)dtype);
+    for (int i = 0; i < k; ++i) {
+        if (!hs[i])
+            return set_error(HIST_EINVAL, "hist_multi_create: handle %d is NULL", i);
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i])
+                return set_error(HIST_EINVAL, "hist_multi_create: handle %d repeats handle %d", i, j);
+        if (hs[i]->device != hs[0]->device)
+            return set_error(HIST_EINVAL, "hist_multi_create: handles on different devices");
+    }
+    hist_multi_s *M = new (std::nothrow) hist_multi_s();
+    if (!M)
+        return set_error(HIST_ENOMEM, "hist_multi_create: host allocation");
+    M->k = k;
+    M->ncols = ncols;
+    M->dtype = dtype;
+    M->device = hs[0]->device;
+    M->num_cu = hs[0]->num_cu;
+    const int lds_max = hs[0]->lds_max;
+
+    std::vector<ExprOp> ops;
+    M->members.resize(k);
+    for (int i = 0; i < k; ++i) {
+        const hist_s *h = hs[i];
+        MultiMember &d = M->members[i];
+        std::memset(&d, 0, sizeof(d));
+        hist_define def;
+        std::memset(&def, 0, sizeof(def));
+        if (defs)
+            def = defs[i];
+        hist_status st = compile_expr(def.filter, ncols, "filter", i, ops, d.filter);
+        for (int a = 0; a < kMaxDims && st == HIST_OK; ++a) {
+            if (a < h->dims)
+                st = compile_expr(def.coord[a], ncols, "coordinate", i, ops, d.coord[a]);
+            else
+                d.coord[a] = ExprRef{(int32_t)ops.size(), 0};
+        }
+        if (st == HIST_OK)
+            st = compile_expr(def.weight, ncols, "weight", i, ops, d.weight);
+        if (st != HIST_OK) {
+            free_multi(M);
+            return st;
+        }
+        for (int a = 0; a < h->dims; ++a) {
+            if (def.coord[a].nops == 0 && a >= ncols) {
+                free_multi(M);
+                return set_error(HIST_EINVAL, "hist_multi_create: member %d axis %d reads column %d "
+                                              "of %d", i, a, a, ncols);
+            }
+        }
+        for (int a = 0; a < kMaxDims; ++a) {
+            d.ax[a] = h->ax[a];
+            d.ax[a].lds_model = -1;
+            d.ax[a].lds_edges = -1;
+        }
+        d.dims = h->dims;
+        d.nstats = h->S;
+        d.total_bins = (int32_t)h->T;
+        d.cnt = h->d_cnt;
+        d.sumw = h->d_sumw;
+        d.sumw2 = h->d_sumw2;
+        d.stats = h->d_stats;
+        d.entries = h->d_entries;
+        d.lds_win = -1;
+        d.copies = 1;
+    }
+
+    // LDS: statistics of every member, then learned models (a learned axis
+    // whose model does not fit falls back to binary search), edge arrays of at
+    // most kStageEdgesMax edges, then whole-histogram copies, smallest
+    // histograms first; members left over use global atomics.
+    int off = 0;
+    for (int i = 0; i < k; ++i) {
+        M->members[i].lds_stats = off;
+        off += kMultiStatsBytes;
+    }
+    for (int i = 0; i < k; ++i) {
+        MultiMember &d = M->members[i];
+        for (int a = 0; a < d.dims; ++a) {
+            AxisDev &ax = d.ax[a];
+            if (ax.kind == AX_LEARNED)
+                ax.kind = AX_BSEARCH;
+            if (ax.kind != AX_UNIFORM && ax.nbins + 1 <= kStageEdgesMax) {
+                const int eb = (ax.nbins + 1) * (int)sizeof(double);
+                if (off + eb <= lds_max / 2) {
+                    ax.lds_edges = off;
+                    off = (off + eb + 15) & ~15;
+                }
+            }
+        }
+    }
+    std::vector<int> order(k);
+    for (int i = 0; i < k; ++i)
+        order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return M->members[a].total_bins < M->members[b].total_bins; });
+    auto bin_bytes = [&](const MultiMember &d) { return d.weight.nops > 0 ? 16 : 4; };
+    for (int i : order) {
+        MultiMember &d = M->members[i];
+        const int64_t need = (int64_t)d.total_bins * bin_bytes(d);
+        if (off + need <= lds_max) {
+            d.lds_win = off;
+            off = (int)((off + need + 15) & ~(int64_t)15);
+            M->window_members.push_back(i);
+        }
+    }
+    // interleaved copies with the LDS left, so lanes of a wave that hit one
+    // bin of a small histogram update different words
+    for (int copies = 2; copies <= 16; copies *= 2) {
+        int64_t extra = 0;
+        for (int i : M->window_members) {
+            const MultiMember &d = M->members[i];
+            extra += (int64_t)d.total_bins * bin_bytes(d) * (copies - d.copies);
+        }
+        if (M->window_members.empty() || off + extra > lds_max)
+            break;
+        // re-lay the windows with `copies` copies each
+        int o2 = k * kMultiStatsBytes;
+        for (int i = 0; i < k; ++i)
+            for (int a = 0; a < M->members[i].dims; ++a) {
+                const AxisDev &ax = M->members[i].ax[a];
+                if (ax.lds_edges >= 0)
+                    o2 = std::max(o2, ax.lds_edges + (((ax.nbins + 1) * 8 + 15) & ~15));
+            }
+        for (int i : M->window_members) {
+            MultiMember &d = M->members[i];
+            d.copies = copies;
+            d.lds_win = o2;
+            o2 = (int)((o2 + (int64_t)d.total_bins * bin_bytes(d) * copies + 15) & ~(int64_t)15);
+        }
+        off = o2;
+    }
+    M->lds = std::max(off, 16);
+
+    hipError_t e = hipMalloc(&M->d_members, sizeof(MultiMember) * k);
+    if (e == hipSuccess)
+        e = hipMalloc(&M->d_ops, sizeof(ExprOp) * std::max<size_t>(ops.size(), 1));
+    if (e == hipSuccess)
+        e = hipMemcpy(M->d_members, M->members.data(), sizeof(MultiMember) * k, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !ops.empty())
+        e = hipMemcpy(M->d_ops, ops.data(), sizeof(ExprOp) * ops.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        free_multi(M);
+        return set_error(e == hipErrorOutOfMemory ? HIST_ENOMEM : HIST_EDEVICE,
+                         "hist_multi_create: %s", hipGetErrorString(e));
+    }
+    *out = M;
+    return HIST_OK;
+}
+
+extern "C" hist_status hist_multi_fill(hist_multi_t *M, const void *const *columns, int64_t n,
+                                       void *stream)
+{
+    if (!M)
+        return set_error(HIST_EINVAL, "hist_multi_fill: NULL plan");
+    if (n < 0)
+        return set_error(HIST_EINVAL, "hist_multi_fill: n < 0");
+    if (n == 0)
+        return HIST_OK;
+    if (!columns)
+        return set_error(HIST_EINVAL, "hist_multi_fill: columns is NULL");
+    MultiArgs a;
+    std::memset(&a, 0, sizeof(a));
+    for (int c = 0; c < M->ncols; ++c) {
+        if (!columns[c])
+            return set_error(HIST_EINVAL, "hist_multi_fill: column %d is NULL", c);
+        a.cols[c] = columns[c];
+    }
+    a.members = M->d_members;
+    a.ops = M->d_ops;
+    a.k = M->k;
+    a.ncols = M->ncols;
+    a.n = n;
+    const int threads = kMaxThreads;
+    const int64_t step = (int64_t)threads * kMultiU;
+    int64_t G = M->num_cu;
+    const int64_t need = (n + step - 1) / step;
+    if (G > need)
+        G = need;
+    int64_t per = (n + G - 1) / G;
+    per = (per + step - 1) / step * step;
+    G = (n + per - 1) / per;
+    a.per_block = per;
+    (void)hipGetLastError();
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const dim3 grid((unsigned)G), block(threads);
+    const size_t lds = (size_t)M->lds;
+    const bool f32 = M->dtype == HIST_F32;
+    if (M->ncols <= 2) {
+        if (f32)
+            hipLaunchKernelGGL((multi_fill_kernel<float, 2>), grid, block, lds, s, a);
+        else
+            hipLaunchKernelGGL((multi_fill_kernel<double, 2>), grid, block, lds, s, a);
+    } else if (M->ncols <= 4) {
+        if (f32)
+            hipLaunchKernelGGL((multi_fill_kernel<float, 4>), grid, block, lds, s, a);
+        else
+            hipLaunchKernelGGL((multi_fill_kernel<double, 4>), grid, block, lds, s, a);
+    } else {
+        if (f32)
+            hipLaunchKernelGGL((multi_fill_kernel<float, kMultiCols>), grid, block, lds, s, a);
+        else
+            hipLaunchKernelGGL((multi_fill_kernel<double, kMultiCols>), grid, block, lds, s, a);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return set_error(HIST_EDEVICE, "hist_multi_fill: launch: %s", hipGetErrorString(e));
+    return HIST_OK;
+}
+
+extern "C" hist_status hist_multi_info(const hist_multi_t *M, int member, int *in_lds, int *copies,
+                                       int *lds_bytes)
+{
+    if (!M || member < 0 || member >= M->k)
+        return set_error(HIST_EINVAL, "hist_multi_info: bad plan or member");
+    if (in_lds)
+        *in_lds = M->members[member].lds_win >= 0 ? 1 : 0;
+    if (copies)
+        *copies = M->members[member].copies;
+    if (lds_bytes)
+        *lds_bytes = M->lds;
+    return HIST_OK;
+}
+
+extern "C" hist_status hist_multi_destroy(hist_multi_t *M)
+{
+    if (!M)
+        return HIST_OK;
+    (void)hipDeviceSynchronize();
+    free_multi(M);
+    return HIST_OK;
+}
