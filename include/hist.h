@@ -145,6 +145,27 @@ HIST_API hist_status hist_destroy(hist_t *h);
 HIST_API hist_status hist_fill(hist_t *h, const void *const *coords, const void *weights,
                       int64_t n, hist_dtype dtype, void *stream);
 
+/* hist_fill for callers that cannot allocate (code under graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same fill, but every
+ * scratch buffer the plan needs comes from one fixed region of
+ * hist_static_scratch_bytes() (64 MiB) that the library holds in each GPU's
+ * memory for the life of the process; it never calls hipMalloc, hipFree or a
+ * synchronization, and never touches the handle's own scratch.  The staging
+ * slots of a merged LDS window must fit the region (else HIST_ENOMEM, nothing
+ * launched); the tiled and partitioned strategies process the events in
+ * chunks whose bin array and tables fit it.  Scratch contents are not kept
+ * between calls (whatever must start at zero is cleared by a kernel).  Every
+ * call on a GPU shares that GPU's region: calls that overlap in time on one
+ * GPU (on different streams, or from different threads) race and give wrong
+ * results; serialize them on one stream.  Asynchronous on `stream`; same
+ * arguments and errors as hist_fill (HIST_ENOMEM as above, HIST_ENOTSUP for a
+ * device ordinal of 64 or more). */
+HIST_API hist_status hist_fill_static(hist_t *h, const void *const *coords, const void *weights,
+                                      int64_t n, hist_dtype dtype, void *stream);
+
+/* Size in bytes of hist_fill_static's per-GPU scratch region. */
+HIST_API int64_t hist_static_scratch_bytes(void);
+
 /* Sizes the handle's scratch for fills of 1..n_max events of `dtype`, with
  * weights (weighted != 0) or without, under the plan choice in force (forced
  * strategy, tuned plan or heuristic): afterwards such fills allocate nothing.

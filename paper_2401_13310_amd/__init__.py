@@ -18,7 +18,7 @@ from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_LEARNE
                    HistFillDesc, check, load)
 
 __all__ = [
-    "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_fill_host", "hist_findbin",
+    "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_fill_static", "hist_static_scratch_bytes", "hist_fill_host", "hist_findbin",
     "hist_reserve",
     "hist_stats", "hist_read", "hist_reset", "hist_train_index", "hist_set_search",
     "hist_index_info", "hist_set_strategy", "hist_set_window", "hist_tune", "hist_plan_info",
@@ -78,6 +78,15 @@ def hist_destroy(h) -> None:
 
 def hist_fill(h, coord_ptrs, weight_ptr, n: int, dtype: int, stream: int) -> None:
     check(load().hist_fill(h, _col_ptrs(coord_ptrs), weight_ptr, n, dtype, stream), "hist_fill")
+
+
+def hist_fill_static(h, coord_ptrs, weight_ptr, n: int, dtype: int, stream: int) -> None:
+    check(load().hist_fill_static(h, _col_ptrs(coord_ptrs), weight_ptr, n, dtype, stream),
+          "hist_fill_static")
+
+
+def hist_static_scratch_bytes() -> int:
+    return int(load().hist_static_scratch_bytes())
 
 
 def hist_fill_host(h, coord_ptrs, weight_ptr, n: int, dtype: int, chunk: int, flags: int,

@@ -48,6 +48,8 @@ PROTOTYPES = {
                           ctypes.POINTER(_H)]),
     "hist_destroy": (_st, [_H]),
     "hist_fill": (_st, [_H, ctypes.POINTER(_P), _P, ctypes.c_int64, ctypes.c_int, _P]),
+    "hist_fill_static": (_st, [_H, ctypes.POINTER(_P), _P, ctypes.c_int64, ctypes.c_int, _P]),
+    "hist_static_scratch_bytes": (ctypes.c_int64, []),
     "hist_fill_host": (_st, [_H, ctypes.POINTER(_P), _P, ctypes.c_int64, ctypes.c_int,
                              ctypes.c_int64, ctypes.c_uint32, _P]),
     "hist_findbin": (_st, [_H, ctypes.POINTER(_P), ctypes.c_int64, ctypes.c_int, _P, _P]),

@@ -372,24 +372,48 @@ static PartLayout part_layout(const hist_s *h, const Plan &p, int64_t mmax, bool
 
 // The four passes of the partitioned strategy over chunks of at most
 // part_chunk events (see partition.hip).
+static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Events per chunk of a partitioned fill whose scratch (bin array plus
+// partition tables) must fit `bytes`: the largest power of two up to the
+// usual chunk that fits, 0 if none of at least 2^12 does.
+static int64_t fixed_part_chunk(const hist_s *h, const Plan &p, bool weighted, size_t bytes)
+{
+    for (int64_t m = part_chunk(h); m >= ((int64_t)1 << 12); m >>= 1)
+        if (up256((size_t)m * 4) + part_layout(h, p, m, weighted).total() <= bytes)
+            return m;
+    return 0;
+}
+
 static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *const *coords,
-                            const void *w, int64_t n, bool f32, hipStream_t s)
+                            const void *w, int64_t n, bool f32, hipStream_t s, const FixedScratch *fx)
 {
     const bool weighted = w != nullptr;
-    const int64_t cap = part_chunk(h);
+    const int64_t cap = fx ? fixed_part_chunk(h, p, weighted, fx->bytes) : part_chunk(h);
+    if (cap <= 0)
+        return set_error(HIST_ENOMEM, "hist_fill_static: the partition tables of this histogram "
+                                      "exceed the %zu-byte scratch", fx->bytes);
     const int64_t mmax = n < cap ? n : cap;
     const int b = p.bucket_bits;
     const PartLayout L = part_layout(h, p, mmax, weighted);
     const int nb = L.nb;
     const int G = p.blocks;
     const size_t table_b = L.table_b, start_b = L.start_b, off_b = L.off_b;
-    hist_status st = ensure_gbins(h, mmax, s);
-    if (st != HIST_OK)
-        return st;
-    st = ensure_part(h, L.total(), s);
-    if (st != HIST_OK)
-        return st;
-    char *base = static_cast<char *>(h->d_part);
+    char *base;
+    int32_t *gbins;
+    if (fx) {
+        gbins = reinterpret_cast<int32_t *>(fx->base);
+        base = fx->base + up256((size_t)mmax * 4);
+    } else {
+        hist_status st = ensure_gbins(h, mmax, s);
+        if (st != HIST_OK)
+            return st;
+        st = ensure_part(h, L.total(), s);
+        if (st != HIST_OK)
+            return st;
+        base = static_cast<char *>(h->d_part);
+        gbins = h->d_gbins;
+    }
     PartArgs P;
     std::memset(&P, 0, sizeof(P));
     P.table = reinterpret_cast<uint32_t *>(base);
@@ -403,7 +427,7 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
     P.nbuckets = nb;
     P.bshift = b;
     P.lds_buckets = p.lds_base;
-    a.gbins = h->d_gbins;
+    a.gbins = gbins;
     const size_t esz = f32 ? 4 : 8;
     const size_t acc_lds = (size_t)(weighted ? 16 : 4) << b;
     const int t0 = h->timing ? timing_event(h) : -1;
@@ -429,8 +453,9 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
         c.part_table = P.table;
         c.part_totals = P.totals;
         c.part_shift = b;
-        // a fill that ran its scatter pass left these totals zero
-        const bool clean = h->part_zero_at == P.totals && nb <= h->part_zero_n;
+        // a fill that ran its scatter pass left these totals zero (never
+        // assumed of fixed scratch, which other fills share)
+        const bool clean = !fx && h->part_zero_at == P.totals && nb <= h->part_zero_n;
         h->part_zero_at = nullptr;
         if (!clean)
             HIPCHK(launch_zero_u32(P.totals, nb, s), "partition totals reset");
@@ -440,8 +465,10 @@ static hist_status run_part(hist_s *h, const Plan &p, FillArgs a, const void *co
         HIPCHK(launch_part_scatter(f32, weighted, kMaxThreads, g, (size_t)part_scatter_lds(nb, weighted),
                                    c, P, s),
                "partition scatter launch");
-        h->part_zero_at = P.totals;
-        h->part_zero_n = nb;
+        if (!fx) {
+            h->part_zero_at = P.totals;
+            h->part_zero_n = nb;
+        }
         // every bucket has at most ceil(records / kPartChunk) chunks
         const int chunks_max = nb + (int)((m + kPartChunk - 1) / kPartChunk);
         HIPCHK(launch_part_accum(weighted, 1024, chunks_max, acc_lds, c, P, s),
@@ -554,7 +581,7 @@ FillArgs hg::base_args(const hist_s *h, const void *const *coords, const void *w
 }
 
 hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, const void *w,
-                         int64_t n, hist_dtype dtype, hipStream_t s)
+                         int64_t n, hist_dtype dtype, hipStream_t s, const FixedScratch *fx)
 {
     // launches are checked with hipGetLastError: start from a clean state, so
     // an error left by an unrelated runtime call is not reported as ours
@@ -564,13 +591,23 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
     FillArgs a = base_args(h, coords, w, n);
     apply_model_offsets(h, a);
     if (p.strategy == HIST_STRAT_PART)
-        return run_part(h, p, a, coords, w, n, f32, s);
+        return run_part(h, p, a, coords, w, n, f32, s, fx);
     if (p.strategy == HIST_STRAT_TILED) {
-        const int64_t cap = tiled_chunk(h);
-        hist_status st = ensure_gbins(h, n < cap ? n : cap, s);
-        if (st != HIST_OK)
-            return st;
-        a.gbins = h->d_gbins;
+        // fixed scratch holds the bin array of a chunk of bytes/4 events
+        int64_t cap = tiled_chunk(h);
+        if (fx)
+            while (cap > 1 && (size_t)cap * 4 > fx->bytes)
+                cap >>= 1;
+        int32_t *gbins;
+        if (fx) {
+            gbins = reinterpret_cast<int32_t *>(fx->base);
+        } else {
+            hist_status st = ensure_gbins(h, n < cap ? n : cap, s);
+            if (st != HIST_OK)
+                return st;
+            gbins = h->d_gbins;
+        }
+        a.gbins = gbins;
         const size_t esz = f32 ? 4 : 8;
         const int t0 = h->timing ? timing_event(h) : -1;
         if (t0 >= 0)
@@ -592,7 +629,7 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
                    "tiled bins launch");
             TileArgs t;
             std::memset(&t, 0, sizeof(t));
-            t.gbins = h->d_gbins;
+            t.gbins = gbins;
             t.w = c.w;
             t.n = m;
             t.tile_len = p.win_len;
@@ -631,10 +668,18 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
     a.epoch_iters = p.epoch_iters;
     a.per_block = p.per_block;
     if (p.merge == MERGE_STAGE) {
-        hist_status st = ensure_stage(h, stage_bytes_for(p), s);
-        if (st != HIST_OK)
-            return st;
-        a.stage = h->d_stage;
+        if (fx) {
+            if (stage_bytes_for(p) > fx->bytes)
+                return set_error(HIST_ENOMEM, "hist_fill_static: the staging slots of this plan (%zu "
+                                              "bytes) exceed the %zu-byte scratch",
+                                 stage_bytes_for(p), fx->bytes);
+            a.stage = fx->base;
+        } else {
+            hist_status st = ensure_stage(h, stage_bytes_for(p), s);
+            if (st != HIST_OK)
+                return st;
+            a.stage = h->d_stage;
+        }
         a.stage_stride = stage_stride_for(p);
     }
     const int t0 = h->timing ? timing_event(h) : -1;
@@ -672,6 +717,63 @@ extern "C" hist_status hist_fill(hist_t *h, const void *const *coords, const voi
     Plan p = make_plan(h, n, dtype, weights != nullptr);
     return run_plan(h, p, coords, weights, n, dtype, s);
 }
+
+// ------------------------------------------------ fills that allocate nothing --
+
+// Scratch of hist_fill_static: one region per device (every GPU the library
+// runs on holds its copy until the process ends), shared by every call on
+// that device.  In host code `scratch` names a host-side stand-in; kernels get
+// the device address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxStaticDevices] = {};
+}  // namespace
+
+// Device address of the current device's scratch, looked up once per device.
+static hist_status static_scratch(FixedScratch &fx)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return hip_fail(hipGetLastError(), "hist_fill_static: current device");
+    if (dev < 0 || dev >= kMaxStaticDevices)
+        return set_error(HIST_ENOTSUP, "hist_fill_static: device %d beyond %d", dev, kMaxStaticDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                            "hist_fill_static: scratch address");
+        g_static_ptr[dev] = ptr;
+    }
+    fx.base = static_cast<char *>(g_static_ptr[dev]);
+    fx.bytes = kStaticScratchBytes;
+    return HIST_OK;
+}
+
+extern "C" hist_status hist_fill_static(hist_t *h, const void *const *coords, const void *weights,
+                                        int64_t n, hist_dtype dtype, void *stream)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_fill_static: NULL handle");
+    if (dtype != HIST_F64 && dtype != HIST_F32)
+        return set_error(HIST_EINVAL, "hist_fill_static: unknown dtype %d", (int)dtype);
+    hist_status st = check_coords(h, coords, n, "hist_fill_static");
+    if (st != HIST_OK || n == 0)
+        return st;
+    FixedScratch fx;
+    st = static_scratch(fx);
+    if (st != HIST_OK)
+        return st;
+    const Plan p = make_plan(h, n, dtype, weights != nullptr);
+    return run_plan(h, p, coords, weights, n, dtype, static_cast<hipStream_t>(stream), &fx);
+}
+
+extern "C" int64_t hist_static_scratch_bytes(void) { return (int64_t)kStaticScratchBytes; }
 
 extern "C" hist_status hist_reserve(hist_t *h, int64_t n_max, hist_dtype dtype, int weighted,
                                     void *stream)

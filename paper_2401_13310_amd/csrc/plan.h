@@ -112,8 +112,15 @@ Plan make_plan(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted);
 Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted,
                       const PlanChoice &c);
 int timing_event(hist_s *h);
+// A fixed device region that replaces a fill's scratch (hist_fill_static):
+// the staging slots, or the bin array and partition tables of chunks sized to
+// fit it.
+struct FixedScratch {
+    char *base;
+    size_t bytes;
+};
 hist_status run_plan(hist_s *h, const Plan &p, const void *const *coords, const void *w,
-                     int64_t n, hist_dtype dtype, hipStream_t s);
+                     int64_t n, hist_dtype dtype, hipStream_t s, const FixedScratch *fx = nullptr);
 size_t stage_bytes_for(const Plan &p);
 int64_t stage_stride_for(const Plan &p);
 int64_t tiled_chunk(const hist_s *h);
