@@ -390,6 +390,7 @@ HIST_API hist_status hist_multi_create(int k, hist_t *const *hs, const hist_defi
  * to n contiguous values each.  Every member adds the events its filter keeps
  * (bins, statistics, entries), as hist_fill of its defined coordinates and
  * weights would.  Asynchronous on `stream`; allocates nothing (capture-safe).
+ * Weights accumulate in binary64 (also for handles made with HIST_F_ACC_F32C).
  * Errors: HIST_EINVAL (NULL plan or column, n < 0), HIST_EDEVICE. */
 HIST_API hist_status hist_multi_fill(hist_multi_t *m, const void *const *columns, int64_t n,
                                      void *stream);

@@ -15,7 +15,8 @@ import numpy as np
 from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_LEARNED, HIST_F_NO_ALLOC,
                    HIST_HOST_PINNED, HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED, HIST_STRAT_AUTO, HIST_STRAT_GLOBAL,
                    HIST_STRAT_LDS, HIST_STRAT_PART, HIST_STRAT_TILED, STRAT_NAMES, HistAxis, HistError,
-                   HistFillDesc, check, load)
+                   HistDefine, HistExpr, HistFillDesc, HistOp, check, load)
+from .expr import OPS, parse
 
 __all__ = [
     "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_fill_static", "hist_static_scratch_bytes", "hist_fill_host", "hist_findbin",
@@ -24,6 +25,8 @@ __all__ = [
     "hist_index_info", "hist_set_strategy", "hist_set_window", "hist_tune", "hist_plan_info",
     "hist_timing", "hist_timing_read", "hist_set_threads",
     "hist_batch_create", "hist_batch_launch", "hist_batch_launch_eager", "hist_batch_destroy",
+    "hist_multi_create", "hist_multi_fill", "hist_multi_info", "hist_multi_destroy", "Multi",
+    "OPS", "parse",
     "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_F_NO_ALLOC", "HIST_HOST_PINNED",
     "HIST_STRAT_AUTO",
     "HIST_STRAT_LDS", "HIST_STRAT_GLOBAL", "HIST_STRAT_TILED", "HIST_STRAT_PART", "HIST_SEARCH_BINARY",
@@ -205,6 +208,65 @@ def hist_batch_destroy(b) -> None:
     check(load().hist_batch_destroy(b), "hist_batch_destroy")
 
 
+def _expr_struct(ops, keep):
+    e = HistExpr()
+    if not ops:
+        e.ops = None
+        e.nops = 0
+        return e
+    arr = (HistOp * len(ops))()
+    for i, (op, col, value) in enumerate(ops):
+        arr[i].op = int(op)
+        arr[i].col = int(col)
+        arr[i].value = float(value)
+    keep.append(arr)
+    e.ops = ctypes.cast(arr, ctypes.POINTER(HistOp))
+    e.nops = len(ops)
+    return e
+
+
+def _define_structs(defs, keep):
+    arr = (HistDefine * len(defs))()
+    for i, d in enumerate(defs):
+        d = d or {}
+        arr[i].filter = _expr_struct(d.get("filter"), keep)
+        coords = d.get("coords") or []
+        for a in range(3):
+            arr[i].coord[a] = _expr_struct(coords[a] if a < len(coords) else None, keep)
+        arr[i].weight = _expr_struct(d.get("weight"), keep)
+    return arr
+
+
+def hist_multi_create(handles, defs, ncols: int, dtype: int):
+    """defs: None, or one dict per handle with optional "filter", "coords"
+    (list per axis) and "weight", each a list of (op, col, value)."""
+    k = len(handles)
+    harr = (ctypes.c_void_p * k)(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                  for h in handles])
+    keep = []
+    darr = None if defs is None else _define_structs(defs, keep)
+    m = ctypes.c_void_p()
+    check(load().hist_multi_create(k, harr, darr, ncols, dtype, ctypes.byref(m)),
+          "hist_multi_create")
+    return m
+
+
+def hist_multi_fill(m, col_ptrs, n: int, stream: int) -> None:
+    arr = (ctypes.c_void_p * max(1, len(col_ptrs)))(*col_ptrs)
+    check(load().hist_multi_fill(m, arr, n, stream), "hist_multi_fill")
+
+
+def hist_multi_info(m, member: int) -> dict:
+    in_lds, copies, lds = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(load().hist_multi_info(m, member, ctypes.byref(in_lds), ctypes.byref(copies),
+                                 ctypes.byref(lds)), "hist_multi_info")
+    return {"in_lds": bool(in_lds.value), "copies": copies.value, "lds_bytes": lds.value}
+
+
+def hist_multi_destroy(m) -> None:
+    check(load().hist_multi_destroy(m), "hist_multi_destroy")
+
+
 # ---- convenience wrapper over torch tensors ---------------------------------
 
 def _check_cols(coords, weights):
@@ -334,6 +396,61 @@ class Hist:
 
     def timing_read(self) -> dict:
         return hist_timing_read(self._h)
+
+
+class Multi:
+    """One pass over shared columns filling several histograms, each with an
+    optional filter, computed coordinates and weight (hist_define).  defs
+    entries may give programs as infix strings over `columns` names."""
+
+    def __init__(self, hists, defs=None, columns=("c0",), dtype: int = HIST_F64):
+        self.columns = list(columns)
+        self.hists = list(hists)
+        prog = None
+        if defs is not None:
+            prog = []
+            for d in defs:
+                d = dict(d or {})
+                out = {}
+                for key in ("filter", "weight"):
+                    if d.get(key) is not None:
+                        out[key] = self._ops(d[key])
+                if d.get("coords") is not None:
+                    out["coords"] = [None if c is None else self._ops(c) for c in d["coords"]]
+                prog.append(out)
+        self.dtype = dtype
+        self._m = hist_multi_create([h.handle for h in self.hists], prog, len(self.columns), dtype)
+
+    def _ops(self, e):
+        return parse(e, self.columns) if isinstance(e, str) else list(e)
+
+    def fill(self, cols, stream=None):
+        cols = list(cols)
+        if len(cols) != len(self.columns):
+            raise ValueError("need %d columns" % len(self.columns))
+        import torch
+        n = cols[0].numel()
+        want = torch.float32 if self.dtype == HIST_F32 else torch.float64
+        for c in cols:
+            if not c.is_cuda or not c.is_contiguous() or c.dim() != 1 or c.numel() != n:
+                raise ValueError("columns must be contiguous 1-D GPU tensors of equal length")
+            if c.dtype != want:
+                raise TypeError("the plan was made for %s columns" % want)
+        hist_multi_fill(self._m, [c.data_ptr() for c in cols], n, _stream_ptr(stream))
+
+    def info(self, member: int) -> dict:
+        return hist_multi_info(self._m, member)
+
+    def close(self):
+        if getattr(self, "_m", None) is not None and self._m.value:
+            hist_multi_destroy(self._m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

@@ -36,6 +36,18 @@ class HistFillDesc(ctypes.Structure):
                 ("n", ctypes.c_int64), ("dtype", ctypes.c_int)]
 
 
+class HistOp(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("col", ctypes.c_int32), ("value", ctypes.c_double)]
+
+
+class HistExpr(ctypes.Structure):
+    _fields_ = [("ops", ctypes.POINTER(HistOp)), ("nops", ctypes.c_int32)]
+
+
+class HistDefine(ctypes.Structure):
+    _fields_ = [("filter", HistExpr), ("coord", HistExpr * 3), ("weight", HistExpr)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -80,6 +92,12 @@ PROTOTYPES = {
     "hist_batch_launch": (_st, [_H, _P]),
     "hist_batch_launch_eager": (_st, [_H, _P]),
     "hist_batch_destroy": (_st, [_H]),
+    "hist_multi_create": (_st, [ctypes.c_int, ctypes.POINTER(_H), ctypes.POINTER(HistDefine),
+                                ctypes.c_int, ctypes.c_int, ctypes.POINTER(_H)]),
+    "hist_multi_fill": (_st, [_H, ctypes.POINTER(_P), ctypes.c_int64, _P]),
+    "hist_multi_info": (_st, [_H, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "hist_multi_destroy": (_st, [_H]),
     "hist_nbins_total": (ctypes.c_int64, [_H]),
     "hist_nstats": (ctypes.c_int, [_H]),
     "hist_strerror": (ctypes.c_char_p, [ctypes.c_int]),

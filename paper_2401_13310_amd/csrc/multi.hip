@@ -18,7 +18,7 @@
 // program, so the host stores it with the operation and the kernel dispatches
 // on (depth, operation): every stack slot is then a register named at compile
 // time.  Programs and depths are the same for every lane, so the dispatch is
-// scalar branching, paid once per batch of events.
+// scalar branching, paid once per wave and event slot.
 #include "../../include/hist.h"
 #include "device_common.h"
 #include "kernels.h"
@@ -34,7 +34,7 @@ constexpr int kMultiMembers = 16;
 constexpr int kMultiCols = 8;
 constexpr int kExprStack = 6;
 constexpr int kExprMaxOps = 32;
-constexpr int kMultiU = 2;           // events per thread per batch
+constexpr int kMultiU = 1;           // events per thread per batch
 constexpr int kMultiStatsBytes = 96; // per member: kMaxStats doubles, then the kept count
 
 struct ExprOp {
