@@ -257,10 +257,14 @@ HIST_API hist_status hist_index_info(hist_t *h, int axis, int *segments, int *fe
 HIST_API hist_status hist_set_strategy(hist_t *h, int strategy, int blocks, int subhists);
 
 /* Autotuner: times the candidate plans on the given sample with HIP events on
- * `stream`, keeps the fastest for this histogram shape and remembers it in a
- * process-wide cache keyed by the shape.  It also picks the LDS window of bins
- * with the largest sample mass.  The histogram contents are restored to what
- * they were before the call.  Synchronizes; HIST_ECAPTURE while capturing. */
+ * `stream` (strategy, threads per workgroup, workgroups per CU, merge), then
+ * refines the chosen one a knob at a time (interleaved LDS copies 1..64 of a
+ * whole-histogram window, events per thread 1, 2, 4, 8 where a shape variant
+ * exists), keeps the fastest for this histogram shape and remembers it in a
+ * process-wide cache keyed by the shape; hist_batch_create applies it to
+ * members of that shape.  It also picks the LDS window of bins with the
+ * largest sample mass.  The histogram contents are restored to what they
+ * were before the call.  Synchronizes; HIST_ECAPTURE while capturing. */
 HIST_API hist_status hist_tune(hist_t *h, const void *const *coords, const void *weights, int64_t n,
                       hist_dtype dtype, void *stream);
 
@@ -279,6 +283,23 @@ HIST_API hist_status hist_set_window(hist_t *h, int64_t window_lo, int merge);
 /* Fixes the threads per workgroup of later fills (0 = heuristic; 256, 512 or
  * 1024).  Used by tests and benchmarks to pin a plan. */
 HIST_API hist_status hist_set_threads(hist_t *h, int threads);
+
+/* Launch shape of later fills (the paper's tuning study, Sec. 4.3, varies the
+ * elements each work-item reduces and fuses the statistics reductions):
+ * unroll = events per thread and loop iteration of the fill kernel (0 =
+ * heuristic, or 1, 2, 4, 8); stats_ept = 0 keeps the statistics fused into
+ * the fill pass, 1, 4 or 16 computes them instead with one reduction kernel
+ * per statistic that re-reads the columns, with that many events per thread.
+ * Variants exist for one binary64 axis (fixed-width or learned index with
+ * unit weights, edges staged in LDS, fixed-width with weights) under the LDS
+ * and global strategies; other fills keep their heuristic shape.  Results
+ * are the same within the tolerance of the summation order. */
+HIST_API hist_status hist_set_shape(hist_t *h, int unroll, int stats_ept);
+
+/* Shape the next fill of n events would use: events per thread, statistics
+ * kernels' events per thread (0 = fused), threads per workgroup. */
+HIST_API hist_status hist_plan_shape(hist_t *h, int64_t n, hist_dtype dtype, int weighted,
+                                     int *unroll, int *stats_ept, int *threads);
 
 /* Kernel timing for benchmarks: while enabled, hist_fill records HIP events on
  * its stream around the fill kernel and around the merge-reduction kernel.

@@ -23,7 +23,7 @@ __all__ = [
     "hist_reserve",
     "hist_stats", "hist_read", "hist_reset", "hist_train_index", "hist_set_search",
     "hist_index_info", "hist_set_strategy", "hist_set_window", "hist_tune", "hist_plan_info",
-    "hist_timing", "hist_timing_read", "hist_set_threads",
+    "hist_timing", "hist_timing_read", "hist_set_threads", "hist_set_shape", "hist_plan_shape",
     "hist_batch_create", "hist_batch_launch", "hist_batch_launch_eager", "hist_batch_destroy",
     "hist_multi_create", "hist_multi_fill", "hist_multi_info", "hist_multi_destroy", "Multi",
     "OPS", "parse",
@@ -173,6 +173,17 @@ def hist_plan_info(h, n: int, dtype: int, weighted: bool) -> dict:
 
 def hist_set_threads(h, threads: int) -> None:
     check(load().hist_set_threads(h, threads), "hist_set_threads")
+
+
+def hist_set_shape(h, unroll: int = 0, stats_ept: int = 0) -> None:
+    check(load().hist_set_shape(h, unroll, stats_ept), "hist_set_shape")
+
+
+def hist_plan_shape(h, n: int, dtype: int, weighted: bool) -> dict:
+    u, e, t = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    check(load().hist_plan_shape(h, n, dtype, int(bool(weighted)), ctypes.byref(u), ctypes.byref(e),
+                                 ctypes.byref(t)), "hist_plan_shape")
+    return {"unroll": u.value, "stats_ept": e.value, "threads": t.value}
 
 
 def hist_timing(h, enable: bool) -> None:
@@ -390,6 +401,12 @@ class Hist:
 
     def set_threads(self, threads: int):
         hist_set_threads(self._h, threads)
+
+    def set_shape(self, unroll: int = 0, stats_ept: int = 0):
+        hist_set_shape(self._h, unroll, stats_ept)
+
+    def plan_shape(self, n: int, dtype: int = HIST_F64, weighted: bool = False) -> dict:
+        return hist_plan_shape(self._h, n, dtype, weighted)
 
     def timing(self, enable: bool = True):
         hist_timing(self._h, enable)

@@ -84,6 +84,10 @@ PROTOTYPES = {
                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)]),
     "hist_set_threads": (_st, [_H, ctypes.c_int]),
+    "hist_set_shape": (_st, [_H, ctypes.c_int, ctypes.c_int]),
+    "hist_plan_shape": (_st, [_H, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                              ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                              ctypes.POINTER(ctypes.c_int)]),
     "hist_timing": (_st, [_H, ctypes.c_int]),
     "hist_timing_read": (_st, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                ctypes.POINTER(ctypes.c_int64)]),

@@ -429,17 +429,26 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         fa.copies = 1;
         const int ks = kind_set(h->dims, h->ax);
         int bacc = d.weights ? BA_F64 : BA_U32;
-        if (h->T * bytes <= avail) {
+        // a plan hist_tune chose for this handle's shape decides between LDS,
+        // partitioned and global accumulation, and the LDS copies
+        PlanChoice tc;
+        const bool tuned = tuned_choice(h, d.weights != nullptr, d.dtype == HIST_F32, tc);
+        const bool tuned_global = tuned && tc.strategy == HIST_STRAT_GLOBAL;
+        const bool tuned_part = tuned && tc.strategy == HIST_STRAT_PART;
+        if (h->T * bytes <= avail && !tuned_global && !tuned_part) {
             m.acc = d.weights ? ACC_F64 : ACC_U32;
             m.win_len = (int32_t)h->T;
             // interleaved copies for small histograms, within 32 KB so the
             // per-tile zeroing and merge stay small next to the tile
             const int64_t fit = std::min<int64_t>(avail, 32768) / (h->T * bytes);
             m.copies = (int32_t)std::min<int64_t>(64, std::max<int64_t>(1, fit));
+            if (tuned && tc.copies > 0)
+                m.copies = (int32_t)std::min<int64_t>(std::max<int64_t>(1, avail / (h->T * bytes)),
+                                                      tc.copies);
             fa.win_len = m.win_len;
             fa.copies = m.copies;
             max_window_bytes = std::max(max_window_bytes, (int)(h->T * bytes * m.copies));
-        } else if (part_ok && d.n >= kPartMinEvents && d.n <= kPartMaxEvents) {
+        } else if (part_ok && d.n >= kPartMinEvents && d.n <= kPartMaxEvents && !tuned_global) {
             bacc = d.weights ? BA_PCOUNT_W : BA_PCOUNT;
             m.acc = kAccPart;
             m.bshift = pbits;

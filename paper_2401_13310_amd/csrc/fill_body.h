@@ -236,7 +236,7 @@ __device__ __forceinline__ void load_batch(const __amdgpu_buffer_rsrc_t (&rx)[D]
 // `nin` (the w and w^2 statistics) instead of adding 1.0 twice.  Events
 // outside the LDS window are handled after the batch's LDS adds, in a branch
 // the wave skips when none of its lanes has one.
-template <int D, typename T, int ACC, bool W, int U, int KS, bool FULL, typename Prefetch>
+template <int D, typename T, int ACC, bool W, int U, int KS, bool FULL, bool ST, typename Prefetch>
 __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uint32_t *win,
                                               const T (&cx)[U][D], const T (&cw)[U],
                                               uint32_t base, uint32_t len, int cp,
@@ -307,15 +307,17 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
         // statistics of in-range events: excluded events add exact zeros
         // (their coordinates and weight are masked, so no inf or NaN enters)
         const bool take = ok && inside;
-        double xm[D];
+        if (ST) {
+            double xm[D];
 #pragma unroll
-        for (int a = 0; a < D; ++a)
-            xm[a] = take ? xe[a] : 0.0;
-        if (W) {
-            stats_add<D>(st, xm, take ? w : 0.0);
-        } else {
-            stats_add_unit<D>(st, xm);
-            nin += take ? 1u : 0u;
+            for (int a = 0; a < D; ++a)
+                xm[a] = take ? xe[a] : 0.0;
+            if (W) {
+                stats_add<D>(st, xm, take ? w : 0.0);
+            } else {
+                stats_add_unit<D>(st, xm);
+                nin += take ? 1u : 0u;
+            }
         }
         const uint32_t l = (uint32_t)(g - A.win_lo);
         const bool inw = l < wlen;
@@ -381,8 +383,9 @@ __device__ __forceinline__ void process_batch(const FillArgs &A, char *smem, uin
 // learned models, zero the LDS window, the pipelined loop over the events,
 // then the statistics and the merge of the window (into staging slot or
 // count-table column `col` of `cols`).  The fill kernel runs it once per
-// block; the batch kernel once per tile.
-template <int D, typename T, int ACC, bool W, int U, int KS>
+// block; the batch kernel once per tile.  ST false leaves the statistics to
+// separate reduction kernels (the launch-shape study).
+template <int D, typename T, int ACC, bool W, int U, int KS, bool ST = true>
 __device__ __forceinline__ void fill_range(const FillArgs &A, char *smem, int64_t start, int64_t end,
                                            int col, int cols)
 {
@@ -431,7 +434,7 @@ __device__ __forceinline__ void fill_range(const FillArgs &A, char *smem, int64_
     // partial last batch (if any) in a loop of its own
     auto iteration = [&](uint32_t base, auto full) {
         T nx[U][D], nw[U];
-        process_batch<D, T, ACC, W, U, KS, decltype(full)::value>(
+        process_batch<D, T, ACC, W, U, KS, decltype(full)::value, ST>(
             A, smem, win, cx, cw, base, len, cp, st, nin, gb,
             [&] { load_batch<D, T, W, U>(xb, wb, base + step, nx, nw); });
         if (ACC == ACC_U16 && ++it == A.epoch_iters) {
@@ -458,7 +461,8 @@ __device__ __forceinline__ void fill_range(const FillArgs &A, char *smem, int64_
         st[1] = (double)nin;
     }
     __syncthreads();
-    reduce_stats<NS>(st, reinterpret_cast<double *>(smem), A.stats);
+    if (ST)
+        reduce_stats<NS>(st, reinterpret_cast<double *>(smem), A.stats);
     merge_window<ACC>(win, A, col, cols);
     cache_flush<W>(A, smem);
 }

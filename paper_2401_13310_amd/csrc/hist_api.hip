@@ -685,8 +685,16 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
     const int t0 = h->timing ? timing_event(h) : -1;
     if (t0 >= 0)
         HIPCHK(hipEventRecord(h->ev_pool[t0], s), "timing event");
-    HIPCHK(launch_fill(h->dims, f32, p.acc, weighted, p.threads, p.blocks, (size_t)p.lds, a, s),
-           "fill launch");
+    if (p.shape) {
+        HIPCHK(launch_fill_shape(p.acc, weighted, kind_set(h->dims, a.ax), p.unroll, p.stats_ept == 0,
+                                 p.threads, p.blocks, (size_t)p.lds, a, s),
+               "fill launch");
+        if (p.stats_ept > 0)
+            HIPCHK(launch_stats_separate(weighted, p.stats_ept, h->num_cu, a, s), "statistics launch");
+    } else {
+        HIPCHK(launch_fill(h->dims, f32, p.acc, weighted, p.threads, p.blocks, (size_t)p.lds, a, s),
+               "fill launch");
+    }
     const int t1 = h->timing ? timing_event(h) : -1;
     if (t1 >= 0) {
         HIPCHK(hipEventRecord(h->ev_pool[t1], s), "timing event");

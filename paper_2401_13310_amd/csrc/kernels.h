@@ -177,6 +177,12 @@ void allow_big_lds_ptr(const void *kernel);
 hipError_t launch_fill(int dims, bool f32, int acc, bool weighted, int threads, int blocks,
                        size_t lds, const FillArgs &a, hipStream_t s);
 hipError_t launch_stage_reduce(int acc, int blocks_used, const FillArgs &a, hipStream_t s);
+// Launch-shape variants (fill_shape.hip): events per thread 1, 2, 4, 8 and
+// statistics fused or left to separate reduction kernels.
+bool fill_shape_supported(int dims, bool f32, int acc, bool weighted, int ks, int unroll);
+hipError_t launch_fill_shape(int acc, bool weighted, int ks, int unroll, bool fused_stats,
+                             int threads, int blocks, size_t lds, const FillArgs &a, hipStream_t s);
+hipError_t launch_stats_separate(bool weighted, int ept, int num_cu, const FillArgs &a, hipStream_t s);
 hipError_t launch_findbin(int dims, bool f32, int threads, int blocks, size_t lds,
                           const FillArgs &a, int32_t *out, hipStream_t s);
 hipError_t launch_tiled_bins(int dims, bool f32, bool weighted, int threads, int blocks,

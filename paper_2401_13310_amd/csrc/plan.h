@@ -35,6 +35,10 @@ struct Plan {
     int lds_cache = -1;              // out-of-window hot-bin cache offset, -1: none
     int cache_slots = 0;
     int bucket_bits = 0;             // PART: log2 of the bucket width in bins
+    int unroll = 0;                  // events per thread and iteration of the fill kernel
+    bool shape = false;              // launch through the shape variants (fill_shape.hip)
+    int stats_ept = 0;               // 0: statistics fused; else separate kernels, this many
+                                     // events per thread
 };
 
 // Choices the autotuner (or a test) fixes for a shape; 0 / -1 mean "heuristic".
@@ -47,6 +51,8 @@ struct PlanChoice {
     int64_t win_lo = -1;
     int threads = 0;         // threads per workgroup (0: heuristic)
     int bucket_bits = 0;     // PART: log2 bucket width (0: heuristic)
+    int unroll = 0;          // events per thread (0: heuristic; 1, 2, 4, 8 where a variant exists)
+    int stats_ept = 0;       // 0: fused statistics; 1, 4, 16: separate reduction kernels
 };
 
 }  // namespace hg
@@ -109,6 +115,8 @@ int apply_model_offsets(const hist_s *h, FillArgs &a);
 // `off` on; returns the first free byte (16-aligned).
 int lds_axis_layout(int dims, AxisDev *ax, int off);
 Plan make_plan(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted);
+// The plan choice hist_tune stored for this handle or its shape, if any.
+bool tuned_choice(const hist_s *h, bool weighted, bool f32, PlanChoice &out);
 Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted,
                       const PlanChoice &c);
 int timing_event(hist_s *h);

@@ -217,7 +217,21 @@ Plan plan_from_choice(const hist_s *h, int64_t n, hist_dtype dtype, bool weighte
         p.lds = p.lds_base + window_bytes(acc, len, copies);
     }
 
-    const int U = unroll_of(h, f32, weighted, p.acc);
+    int U = unroll_of(h, f32, weighted, p.acc);
+    if ((c.unroll > 0 || c.stats_ept > 0) &&
+        (p.strategy == HIST_STRAT_LDS || p.strategy == HIST_STRAT_GLOBAL)) {
+        const int ks = kind_set(h->dims, h->ax);
+        int u = c.unroll;
+        if (u <= 0)   // separate statistics at the heuristic count (or the next variant below)
+            for (u = 8; u > 1 && u > U; u >>= 1) {
+            }
+        if (fill_shape_supported(h->dims, f32, p.acc, weighted, ks, u)) {
+            U = u;
+            p.shape = true;
+            p.stats_ept = c.stats_ept;
+        }
+    }
+    p.unroll = U;
     const int64_t step = (int64_t)p.threads * U;
     int bpc = c.blocks_per_cu > 0 ? c.blocks_per_cu : (p.lds > h->lds_max / 2 ? 1 : 2);
     if (p.lds * bpc > h->lds_max)
@@ -277,6 +291,21 @@ ShapeKey shape_key(const hist_s *h, bool weighted, bool f32)
 }
 }  // namespace
 
+bool tuned_choice(const hist_s *h, bool weighted, bool f32, PlanChoice &out)
+{
+    auto it = h->tuned.find(std::make_tuple(weighted ? 1 : 0, f32 ? 1 : 0, 0));
+    if (it != h->tuned.end()) {
+        out = it->second;
+        return true;
+    }
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto jt = g_cache.find(shape_key(h, weighted, f32));
+    if (jt == g_cache.end())
+        return false;
+    out = jt->second;
+    return true;
+}
+
 Plan make_plan(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted)
 {
     PlanChoice c = h->forced;
@@ -290,6 +319,11 @@ Plan make_plan(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted)
             if (jt != g_cache.end())
                 c = jt->second;
         }
+        // a shape fixed by hist_set_shape applies over a tuned choice
+        if (h->forced.unroll > 0)
+            c.unroll = h->forced.unroll;
+        if (h->forced.stats_ept > 0)
+            c.stats_ept = h->forced.stats_ept;
     }
     return plan_from_choice(h, n, dtype, weighted, c);
 }
@@ -314,7 +348,37 @@ extern "C" hist_status hist_set_strategy(hist_t *h, int strategy, int blocks, in
     c.win_lo = h->forced.win_lo;
     c.threads = h->forced.threads;
     c.bucket_bits = h->forced.bucket_bits;
+    c.unroll = h->forced.unroll;
+    c.stats_ept = h->forced.stats_ept;
     h->forced = c;
+    return HIST_OK;
+}
+
+extern "C" hist_status hist_set_shape(hist_t *h, int unroll, int stats_ept)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_set_shape: NULL handle");
+    if (unroll != 0 && unroll != 1 && unroll != 2 && unroll != 4 && unroll != 8)
+        return set_error(HIST_EINVAL, "hist_set_shape: unroll must be 0, 1, 2, 4 or 8");
+    if (stats_ept != 0 && stats_ept != 1 && stats_ept != 4 && stats_ept != 16)
+        return set_error(HIST_EINVAL, "hist_set_shape: stats_ept must be 0, 1, 4 or 16");
+    h->forced.unroll = unroll;
+    h->forced.stats_ept = stats_ept;
+    return HIST_OK;
+}
+
+extern "C" hist_status hist_plan_shape(hist_t *h, int64_t n, hist_dtype dtype, int weighted,
+                                       int *unroll, int *stats_ept, int *threads)
+{
+    if (!h)
+        return set_error(HIST_EINVAL, "hist_plan_shape: NULL handle");
+    const Plan p = make_plan(h, n < 1 ? 1 : n, dtype, weighted != 0);
+    if (unroll)
+        *unroll = p.unroll;
+    if (stats_ept)
+        *stats_ept = p.stats_ept;
+    if (threads)
+        *threads = p.threads;
     return HIST_OK;
 }
 
@@ -519,42 +583,85 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
     heur.strategy = p0.strategy;
     heur.win_lo = win_lo;
     cands.insert(cands.begin(), heur);
-    float best_ms = 1e30f, heur_ms = 1e30f;
-    PlanChoice best = heur;
-    for (size_t ci = 0; ci < cands.size(); ++ci) {
-        const PlanChoice &c = cands[ci];
+    // Best of five timed runs after a warm-up; false when the plan differs
+    // from the choice (the strategy does not apply) or fails.
+    auto time_choice = [&](const PlanChoice &c, float &out) -> bool {
         Plan p = plan_from_choice(h, n, dtype, weighted, c);
         if (p.strategy != c.strategy)
-            continue;
-        st = run_plan(h, p, coords, weights, n, dtype, s);   // warm-up (and allocations)
-        if (st != HIST_OK) {
+            return false;
+        hist_status rs = run_plan(h, p, coords, weights, n, dtype, s);   // warm-up (and allocations)
+        if (rs != HIST_OK) {
             if (std::getenv("HIST_LOG"))
                 fprintf(stderr, "hist_tune: candidate strategy %d bucket_bits %d failed: %s\n",
                         c.strategy, c.bucket_bits, hist_last_error());
-            continue;
+            return false;
         }
         float tmin = 1e30f;
-        for (int r = 0; r < 5; ++r) {
+        for (int r = 0; r < 5 && rs == HIST_OK; ++r) {
             (void)hipEventRecord(e0, s);
-            st = run_plan(h, p, coords, weights, n, dtype, s);
+            rs = run_plan(h, p, coords, weights, n, dtype, s);
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float ms = 0;
             (void)hipEventElapsedTime(&ms, e0, e1);
             tmin = std::min(tmin, ms);
         }
-        if (st != HIST_OK)
+        out = tmin;
+        return rs == HIST_OK;
+    };
+    // the heuristic plan goes first; another candidate replaces it only when
+    // it is clearly faster, so that near-ties do not flip between runs
+    float best_ms = 1e30f, heur_ms = 1e30f;
+    PlanChoice best = heur;
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        float ms;
+        if (!time_choice(cands[ci], ms))
             continue;
         if (ci == 0)
-            heur_ms = tmin;
-        if (tmin < best_ms) {
-            best_ms = tmin;
-            best = c;
+            heur_ms = ms;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cands[ci];
         }
     }
     if (heur_ms <= best_ms * 1.05f) {
         best = heur;
         best_ms = heur_ms;
+    }
+    // Refinement of the chosen LDS or global plan, one knob at a time: the
+    // interleaved copies of a small window (1 .. 64), then the events per
+    // thread (1, 2, 4, 8 where a variant exists).  A change is kept only when
+    // it is at least 3% faster.
+    const Plan pb = plan_from_choice(h, n, dtype, weighted, best);
+    if (pb.strategy == HIST_STRAT_LDS && (pb.acc == ACC_U32 || pb.acc == ACC_F64) &&
+        pb.win_len == h->T) {
+        PlanChoice base = best;
+        for (int r : {1, 2, 4, 8, 16, 32, 64}) {
+            PlanChoice c = base;
+            c.copies = r;
+            if (plan_from_choice(h, n, dtype, weighted, c).copies != r)
+                continue;
+            float ms;
+            if (time_choice(c, ms) && ms < best_ms * 0.97f) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+    }
+    if (pb.strategy == HIST_STRAT_LDS || pb.strategy == HIST_STRAT_GLOBAL) {
+        PlanChoice base = best;
+        for (int u : {1, 2, 4, 8}) {
+            PlanChoice c = base;
+            c.unroll = u;
+            const Plan pu = plan_from_choice(h, n, dtype, weighted, c);
+            if (!pu.shape || pu.unroll != u)
+                continue;
+            float ms;
+            if (time_choice(c, ms) && ms < best_ms * 0.97f) {
+                best_ms = ms;
+                best = c;
+            }
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -566,8 +673,8 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
     }
     if (std::getenv("HIST_LOG"))
         fprintf(stderr, "hist_tune: T=%lld n=%lld -> strategy %d bpc %d merge %d win_lo %lld "
-                        "bucket_bits %d (%.3f ms)\n",
+                        "bucket_bits %d copies %d unroll %d (%.3f ms)\n",
                 (long long)h->T, (long long)n, best.strategy, best.blocks_per_cu, best.merge,
-                (long long)best.win_lo, best.bucket_bits, best_ms);
+                (long long)best.win_lo, best.bucket_bits, best.copies, best.unroll, best_ms);
     return st;
 }

@@ -72,7 +72,7 @@ def _run(hg, names, columns, members, dtype=None, fills=1):
 
 def _columns(n, seed, k=3):
     rng = np.random.default_rng(seed)
-    z = rng.standard_normal((k, n))
+    z = rng.standard_normal((3, n))
     return [z[0], 0.5 * z[0] + z[1], z[2] * 2.0 + 0.3][:k]
 
 
