@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="variable_1d",
                     choices=["variable_1d", "plain_1d", "corr_3d", "precision", "paper_1d",
-                             "batched_64"],
+                             "batched_64", "sweep"],
                     help="variable_1d (default) is the headline and also runs --configs; the "
                          "others time one workload on its own")
     ap.add_argument("--configs", default=",".join(CONFIGS),
@@ -781,6 +781,73 @@ def run_single(args, wl, headline):
     print(json.dumps(out), flush=True)
 
 
+def sweep(args):
+    """The paper's launch-shape questions (Sec. 4.3) on gfx950: events per
+    thread of the fill kernel (1, 2, 4, 8) with fused statistics, and the
+    statistics as separate reduction kernels (one per statistic, re-reading
+    the columns; 1, 4, 16 events per thread) against fused.  One-axis
+    binary64 workloads: plain_1d at 2^27 events (fixed-width, weighted), the
+    variable-bin workload (learned index, 5e7) and the paper's own shape (1000
+    edges on [0, 1], x ~ U[0, 1], 5e7, edges in LDS).  Every variant's counts
+    are compared bit for bit with the default shape's, and its statistics
+    within 1e-12 of the default's scale."""
+    import numpy as np
+    import paper_2401_13310_amd as hg
+    import synth
+    cases = [("plain_1d_2e27", synth.plain_1d(1 << 27)),
+             ("variable_1d", synth.variable_1d(synth.VARIABLE_1D_N)),
+             ("paper_1d", synth.paper_1d(50_000_000))]
+    out = []
+    for name, wl in cases:
+        n = len(wl["coords"][0])
+        cols, w = to_dev(wl)
+        bytes_, _ = alg_bytes(wl, n)
+        ref = None
+        rows = []
+        shapes = [(0, 0)] + [(u, 0) for u in (1, 2, 4, 8)] + [(0, e) for e in (1, 4, 16)]
+        for unroll, ept in shapes:
+            h = hg.Hist(wl["axes"])
+            train_all(h, wl["axes"])
+            h.set_shape(unroll, ept)
+            shape = h.plan_shape(n, weighted=w is not None)
+            step = lambda: h.fill(cols, w)
+            wall, kt = time_fills(h, step, args.steps, args.warmup)
+            ms = kt["fill_ms"] + kt["merge_ms"]
+            h.reset()
+            h.fill(cols, w)
+            sumw, _, entries, st = gpu_result(h)
+            row = {"unroll": shape["unroll"], "stats": "fused" if shape["stats_ept"] == 0 else
+                   "separate, %d events/thread" % shape["stats_ept"],
+                   "requested": [unroll, ept], "kernel_ms": ms,
+                   "ms_per_step": wall * 1e3 / args.steps, "events_per_s": n / (ms * 1e-3),
+                   "frac": bytes_ / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+            if ref is None:
+                ref = (sumw, entries, st)
+                row["default"] = True
+            else:
+                scale = np.maximum(np.abs(ref[2]), 1e-300)
+                row["counts_equal_default"] = bool(np.array_equal(sumw, ref[0]) if w is None
+                                                   else np.allclose(sumw, ref[0], rtol=1e-12, atol=0))
+                row["entries_equal_default"] = entries == ref[1]
+                row["stats_max_rel_diff"] = float(np.max(np.abs(st - ref[2]) / scale))
+            log("sweep %s unroll=%d stats_ept=%d: %.4f ms" % (name, shape["unroll"],
+                                                               shape["stats_ept"], ms))
+            rows.append(row)
+            h.close()
+        fused = [r for r in rows if r["stats"] == "fused"]
+        sep = [r for r in rows if r["stats"] != "fused"]
+        best_f = min(fused, key=lambda r: r["kernel_ms"])
+        worst_f = max(fused, key=lambda r: r["kernel_ms"])
+        best_s = min(sep, key=lambda r: r["kernel_ms"])
+        out.append({"workload": describe(wl, n), "alg_bytes": bytes_, "rows": rows,
+                    "best_unroll": best_f["unroll"],
+                    "best_vs_worst_unroll": worst_f["kernel_ms"] / best_f["kernel_ms"],
+                    "fused_vs_separate": best_s["kernel_ms"] / best_f["kernel_ms"]})
+        del cols, w
+        release()
+    print(json.dumps({"sweep": out, "steps": args.steps, "warmup": args.warmup}), flush=True)
+
+
 def main():
     args = parse()
     if args.ingest:
@@ -792,6 +859,9 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.workload == "sweep":
+        sweep(args)
+        return
     if args.workload == "batched_64":
         out = config_batched(args, cpu_threads())
         out.update({"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
