@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 METRIC = "fill events/s + HBM GB/s fraction; learned vs bsearch FindBin, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 REL = 1e-12
-CONFIGS = ("C1", "C3", "C4", "C5")
+CONFIGS = ("C1", "C3", "C4", "C5", "F1", "F2")
 
 
 def parse():
@@ -771,6 +771,10 @@ def run_single(args, wl, headline):
                     configs["C4_batched_64"] = config_batched(args, threads)
                 elif c == "C5":
                     configs["C5_precision"] = config_precision(args, threads)
+                elif c == "F1":
+                    configs["F1_host_ingest"] = config_host(args)
+                elif c == "F2":
+                    configs["F2_multi_pass"] = config_multi(args, threads)
                 else:
                     raise SystemExit("unknown config %s" % c)
             except (RuntimeError, ValueError, MemoryError) as e:
@@ -779,6 +783,131 @@ def run_single(args, wl, headline):
         if configs:
             out["configs"] = configs
     print(json.dumps(out), flush=True)
+
+
+def _event_ms(fn, reps):
+    """Mean milliseconds of fn() between HIP events on the current stream
+    (host-synchronous calls included)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def config_host(args):
+    """Events in host memory (hist_fill_host) on the variable-bin workload:
+    pageable and page-locked input against the measured host-to-device copy
+    rate of the same bytes; counts against a device-resident fill."""
+    import numpy as np
+    import torch
+
+    import paper_2401_13310_amd as hg
+    wl = build_workload("variable_1d", 0)
+    x = wl["coords"][0]
+    n = x.size
+    nbytes = x.nbytes
+    reps = max(2, min(args.steps, 5))
+    xp = torch.from_numpy(x).pin_memory()
+    xh = torch.from_numpy(x)
+    dst = torch.empty(n, dtype=torch.float64, device="cuda")
+    pinned_copy_ms = _event_ms(lambda: dst.copy_(xp, non_blocking=True), reps)
+    pageable_copy_ms = _event_ms(lambda: dst.copy_(xh), reps)
+    ref = hg.Hist(wl["axes"])
+    train_all(ref, wl["axes"])
+    ref.fill([dst])
+    rs, _, re_, rst = gpu_result(ref)
+    out = {"workload": describe(wl, n), "bytes": nbytes,
+           "h2d_pinned_GBps": nbytes / (pinned_copy_ms * 1e-3) / 1e9,
+           "h2d_pageable_GBps": nbytes / (pageable_copy_ms * 1e-3) / 1e9}
+    for name, cols, pinned in (("pageable", [x], False), ("pinned", [xp], True)):
+        h = hg.Hist(wl["axes"])
+        train_all(h, wl["axes"])
+        h.fill_host(cols, pinned=pinned)          # slots and scratch
+        h.reset()
+        ms = _event_ms(lambda: h.fill_host(cols, pinned=pinned), reps)
+        h.reset()
+        h.fill_host(cols, pinned=pinned)
+        s, _, e, st = gpu_result(h)
+        out[name] = {"ms_per_fill": ms, "events_per_s": n / (ms * 1e-3),
+                     "GBps": nbytes / (ms * 1e-3) / 1e9,
+                     "frac_of_pinned_h2d": (nbytes / (ms * 1e-3) / 1e9) /
+                                           out["h2d_pinned_GBps"],
+                     "counts_equal_device_fill": bool(np.array_equal(s, rs)) and e == re_,
+                     "stats_max_rel_diff": float(np.max(np.abs(st - rst) /
+                                                        np.maximum(np.abs(rst), 1e-300)))}
+        h.close()
+    ref.close()
+    del xp, xh, dst
+    release()
+    return out
+
+
+def config_multi(args, threads):
+    """One pass over the correlated 3D columns filling four histograms (the
+    three 1D projections and r = sqrt(x^2+y^2+z^2) of the events with z > 0)
+    against the same projections filled one by one; every member against the
+    oracle of its defined events."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from oracle import expr as E
+    import paper_2401_13310_amd as hg
+    wl = build_workload("corr_3d", 0)
+    n = len(wl["coords"][0])
+    names = ["x", "y", "z"]
+    cols, _ = to_dev(wl)
+    ax1 = [{"nbins": 100, "xmin": -4.0, "xmax": 4.0}]
+    members = [(ax1, {"coords": ["x"]}), (ax1, {"coords": ["y"]}), (ax1, {"coords": ["z"]}),
+               ([{"nbins": 200, "xmin": 0.0, "xmax": 8.0}],
+                {"filter": "z > 0", "coords": ["sqrt(x*x + y*y + z*z)"]})]
+    hists = [hg.Hist(a) for a, _ in members]
+    plan = hg.Multi(hists, [d for _, d in members], names)
+    reps = max(2, min(args.steps, 10))
+    multi_ms = _event_ms(lambda: plan.fill(cols), reps)
+    proj = [hg.Hist(ax1) for _ in range(3)]
+    three = [hg.Multi([hh], [{"coords": [nm]}], names) for hh, nm in zip(proj, names)]
+    sep_ms = _event_ms(lambda: [p_.fill(cols) for p_ in three], reps)
+    plain = [hg.Hist(ax1) for _ in range(3)]
+    plain_ms = _event_ms(lambda: [hh.fill([c]) for hh, c in zip(plain, cols)], reps)
+    for hh in hists:
+        hh.reset()
+    plan.fill(cols)
+    torch.cuda.synchronize()
+    ok = True
+    worst = 0.0
+    for hh, (axes, d) in zip(hists, members):
+        ops = {"filter": hg.parse(d["filter"], names) if d.get("filter") else None,
+               "coords": [hg.parse(c, names) for c in d["coords"]]}
+        oc, ow = E.apply_define(ops, wl["coords"], len(axes))
+        s, _, e, st = gpu_result(hh)
+        ref = oracle_fill(axes, oc, ow, threads)
+        scale = oracle_scale(axes, oc, ow, threads)
+        ok = ok and e == ref["entries"] and bool(np.array_equal(s, ref["sumw"]))
+        worst = max(worst, float(np.max(np.abs(st - ref["stats"]) /
+                                        np.maximum(np.maximum(np.abs(ref["stats"]), scale), 1e-300))))
+        ok = ok and worst <= REL
+    bytes_ = 3 * 8 * n + sum(hist_bytes(a) for a, _ in members)
+    out = {"workload": "corr_3d columns, %d events: 1D projections x, y, z and r = sqrt(x^2+y^2+z^2)"
+                       " for z > 0 in one pass" % n,
+           "multi_pass_ms": multi_ms, "events_per_s": n / (multi_ms * 1e-3),
+           "roofline": roofline(bytes_, multi_ms),
+           "three_projections_separately_ms": sep_ms,
+           "three_projections_plain_fills_ms": plain_ms,
+           "speedup_vs_plain_fills_of_projections_only": plain_ms / multi_ms,
+           "parity": {"ok": ok, "stats_max_scaled_err": worst,
+                      "what": "every member: counts bit-exact, entries equal, statistics 1e-12"}}
+    for o in [plan] + three:
+        o.close()
+    del cols
+    release()
+    return out
 
 
 def sweep(args):
