@@ -64,6 +64,8 @@ def parse():
                     help="read two rocprofv3 --pmc databases of a --profile run (FETCH_SIZE, "
                          "then WRITE_SIZE), scale each by the copy kernel of known size, and "
                          "record the fill kernel's HBM bytes per launch in --traffic")
+    ap.add_argument("--strategy", default="tuned", choices=["tuned", "lds", "global", "tiled", "part"],
+                    help="profile runs: fix the accumulation strategy instead of tuning")
     ap.add_argument("--profile", action="store_true",
                     help="for counter runs: tune, run --steps fills, then 3 device copies of "
                          "the coordinate column (a copy of known size to scale the counters); "
@@ -344,7 +346,11 @@ def config_single(name, wl, args, threads, flags=0, compare_global=False):
     h = hg.Hist(wl["axes"], flags)
     train_all(h, wl["axes"])
     sample = min(n, 1 << 22)
-    h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
+    if args.strategy == "tuned":
+        h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
+    else:
+        h.set_strategy({"lds": hg.HIST_STRAT_LDS, "global": hg.HIST_STRAT_GLOBAL,
+                        "tiled": hg.HIST_STRAT_TILED, "part": hg.HIST_STRAT_PART}[args.strategy])
     plan = h.plan_info(n, hg.HIST_F64, w is not None)
     wall, kt = time_fills(h, lambda: h.fill(cols, w), args.steps, args.warmup)
     B, per_event = alg_bytes(wl, n)
@@ -714,6 +720,11 @@ def run_single(args, wl, headline):
     }
     if train_ms is not None:
         out["index_train_ms"] = train_ms
+    if headline:
+        out["probes"] = probes(cols[0])
+        read_gbs = out["probes"]["read_GBps"]
+        rl["achievable_read_GBps"] = read_gbs
+        rl["frac_of_achievable_read"] = rl["achieved"] / read_gbs if read_gbs > 0 else None
     if variable and not args.no_bsearch:
         hb = hg.Hist(wl["axes"], flags)
         hb.tune([c[:sample] for c in cols], None if w is None else w[:sample])
@@ -783,6 +794,37 @@ def run_single(args, wl, headline):
         if configs:
             out["configs"] = configs
     print(json.dumps(out), flush=True)
+
+
+def probes(col):
+    """The ceilings of the roofline, measured with the library's probes on
+    this GPU: streaming read bandwidth (over the workload's own column), LDS
+    atomic rates (u32 and binary64 adds, one 1024-thread workgroup per CU)
+    and device-scope atomic rates without return (u64 and binary64 adds to
+    hashed addresses of a 64 MiB array)."""
+    import torch
+
+    import paper_2401_13310_amd as hg
+    stream = torch.cuda.current_stream().cuda_stream
+    nbytes = col.numel() * col.element_size()
+    out = {"read_GBps": hg.hist_probe(hg._lib.HIST_PROBE_READ, col.data_ptr(), nbytes, 10,
+                                      stream)["rate"] / 1e9,
+           "read_bytes": nbytes}
+    clk = 2.4e9
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for name, kind in (("lds_u32", hg._lib.HIST_PROBE_LDS_U32), ("lds_f64", hg._lib.HIST_PROBE_LDS_F64)):
+        r = hg.hist_probe(kind, None, 0, 5, stream)["rate"]
+        out[name + "_Gops"] = r / 1e9
+        out[name + "_lanes_per_clk_per_cu"] = r / clk / cus
+    buf = torch.zeros(8 << 20, dtype=torch.float64, device="cuda")
+    for name, kind in (("global_u64", hg._lib.HIST_PROBE_GLOBAL_U64),
+                       ("global_f64", hg._lib.HIST_PROBE_GLOBAL_F64)):
+        out[name + "_Gops"] = hg.hist_probe(kind, buf.data_ptr(), buf.numel() * 8, 5,
+                                            stream)["rate"] / 1e9
+    del buf
+    out["what"] = ("hist_probe kernels timed with HIP events; per-CU rates assume the 2.4 GHz "
+                   "peak clock and %d CUs" % cus)
+    return out
 
 
 def _event_ms(fn, reps):

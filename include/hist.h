@@ -425,6 +425,31 @@ HIST_API hist_status hist_multi_info(const hist_multi_t *m, int member, int *in_
 /* Frees the plan (synchronizes the device).  NULL is accepted. */
 HIST_API hist_status hist_multi_destroy(hist_multi_t *m);
 
+/* ---- measurement probes ------------------------------------------------------ */
+
+/* What hist_probe measures (the ceilings of the fill's roofline):
+ *   HIST_PROBE_READ        streaming read of `bytes` of `buf` (16-byte
+ *                          non-temporal loads): bytes/s
+ *   HIST_PROBE_LDS_U32     32-bit LDS atomic adds, one 1024-thread workgroup
+ *                          per CU, hashed addresses in 64 KB: lane operations/s
+ *   HIST_PROBE_LDS_F64     the same with binary64 LDS atomic adds
+ *   HIST_PROBE_GLOBAL_U64  device-scope 64-bit atomic adds without return to
+ *                          hashed addresses of `buf` (overwritten): operations/s
+ *   HIST_PROBE_GLOBAL_F64  the same with binary64 atomic adds */
+#define HIST_PROBE_READ       0
+#define HIST_PROBE_LDS_U32    1
+#define HIST_PROBE_LDS_F64    2
+#define HIST_PROBE_GLOBAL_U64 3
+#define HIST_PROBE_GLOBAL_F64 4
+
+/* Runs probe `kind` once to warm up, then `reps` times between HIP events on
+ * `stream`; *rate = work per second, *ms = mean milliseconds per run (may be
+ * NULL).  buf: DEVICE buffer of `bytes` (>= 4096) for the read and global
+ * probes, ignored by the LDS probes.  Synchronizes.  Errors: HIST_EINVAL,
+ * HIST_EDEVICE. */
+HIST_API hist_status hist_probe(int kind, const void *buf, int64_t bytes, int reps, void *stream,
+                                double *rate, double *ms);
+
 /* ---- introspection -------------------------------------------------------- */
 
 HIST_API int64_t hist_nbins_total(const hist_t *h);   /* T, or -1 for NULL */

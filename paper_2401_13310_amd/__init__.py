@@ -19,7 +19,7 @@ from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_LEARNE
 from .expr import OPS, parse
 
 __all__ = [
-    "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_fill_static", "hist_static_scratch_bytes", "hist_fill_host", "hist_findbin",
+    "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_fill_static", "hist_static_scratch_bytes", "hist_fill_host", "hist_probe", "hist_findbin",
     "hist_reserve",
     "hist_stats", "hist_read", "hist_reset", "hist_train_index", "hist_set_search",
     "hist_index_info", "hist_set_strategy", "hist_set_window", "hist_tune", "hist_plan_info",
@@ -86,6 +86,13 @@ def hist_fill(h, coord_ptrs, weight_ptr, n: int, dtype: int, stream: int) -> Non
 def hist_fill_static(h, coord_ptrs, weight_ptr, n: int, dtype: int, stream: int) -> None:
     check(load().hist_fill_static(h, _col_ptrs(coord_ptrs), weight_ptr, n, dtype, stream),
           "hist_fill_static")
+
+
+def hist_probe(kind: int, buf_ptr, nbytes: int, reps: int, stream: int) -> dict:
+    rate, ms = ctypes.c_double(), ctypes.c_double()
+    check(load().hist_probe(kind, buf_ptr, nbytes, reps, stream, ctypes.byref(rate), ctypes.byref(ms)),
+          "hist_probe")
+    return {"rate": rate.value, "ms": ms.value}
 
 
 def hist_static_scratch_bytes() -> int:

@@ -20,6 +20,8 @@ HIST_F_ACC_F32C = 1 << 0
 HIST_F_LEARNED = 1 << 1
 HIST_F_NO_ALLOC = 1 << 2
 HIST_HOST_PINNED = 1 << 0
+(HIST_PROBE_READ, HIST_PROBE_LDS_U32, HIST_PROBE_LDS_F64, HIST_PROBE_GLOBAL_U64,
+ HIST_PROBE_GLOBAL_F64) = range(5)
 HIST_STRAT_AUTO, HIST_STRAT_LDS, HIST_STRAT_GLOBAL, HIST_STRAT_TILED, HIST_STRAT_PART = range(5)
 HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED = 0, 1
 ACC_NAMES = {0: "u32", 1: "u16", 2: "f64", 3: "f32c"}
@@ -102,6 +104,8 @@ PROTOTYPES = {
     "hist_multi_info": (_st, [_H, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                               ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "hist_multi_destroy": (_st, [_H]),
+    "hist_probe": (_st, [ctypes.c_int, _P, ctypes.c_int64, ctypes.c_int, _P,
+                         ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "hist_nbins_total": (ctypes.c_int64, [_H]),
     "hist_nstats": (ctypes.c_int, [_H]),
     "hist_strerror": (ctypes.c_char_p, [ctypes.c_int]),
