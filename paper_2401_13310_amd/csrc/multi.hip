@@ -35,7 +35,7 @@ constexpr int kMultiCols = 8;
 constexpr int kExprStack = 6;
 constexpr int kExprMaxOps = 32;
 constexpr int kMultiU = 1;           // events per thread per batch
-constexpr int kMultiStatsBytes = 96; // per member: kMaxStats doubles, then the kept count
+constexpr int kMultiStatsBytes = 96; // per member: kMaxStats doubles, kept and in-range counts
 
 struct ExprOp {
     int32_t code;    // hist_opcode
@@ -56,7 +56,9 @@ struct MultiMember {
     int32_t nstats;
     int32_t lds_win;      // byte offset of the LDS copy of the histogram, -1: global atomics
     int32_t copies;       // interleaved copies in that LDS region
-    int32_t lds_stats;    // byte offset of the statistics partials and kept count
+    int32_t lds_stats;    // byte offset of the statistics partials, kept and in-range counts
+    int32_t lds_tstats;   // byte offset of per-thread sums [nsums][threads], -1: per-wave reduction
+    int32_t nsums;        // sums per event: all statistics (weighted) or all but the counts
     int32_t total_bins;
     ExprRef filter, coord[kMaxDims], weight;
     uint64_t *cnt;
@@ -252,6 +254,11 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
         uint32_t *st = reinterpret_cast<uint32_t *>(smem + M.lds_stats);
         for (int i = tid; i < kMultiStatsBytes / 4; i += nthr)
             st[i] = 0u;
+        if (M.lds_tstats >= 0) {
+            double *ts = reinterpret_cast<double *>(smem + M.lds_tstats);
+            for (int i = tid; i < M.nsums * nthr; i += nthr)
+                ts[i] = 0.0;
+        }
         if (M.lds_win >= 0) {
             uint32_t *win = reinterpret_cast<uint32_t *>(smem + M.lds_win);
             const int words = M.total_bins * M.copies * (M.weight.nops > 0 ? 4 : 1);
@@ -363,16 +370,19 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
                     gl_add_u64(&M.cnt[g[j]], 1ull);
                 }
             }
-            // statistics of the kept in-range events, reduced per wave into LDS
+            // statistics of the kept in-range events: counts by wave votes,
+            // sums into per-thread LDS partials (or a wave reduction when the
+            // plan had no room for them)
             double st[kMaxStats];
 #pragma unroll
             for (int s = 0; s < kMaxStats; ++s)
                 st[s] = 0.0;
-            uint32_t kept = 0;
+            uint32_t nkept = 0, nin = 0;
 #pragma unroll
             for (int j = 0; j < U; ++j) {
-                kept += keep[j] ? 1u : 0u;
                 const bool take = keep[j] && inside[j];
+                nkept += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(keep[j]));
+                nin += (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(take));
                 double xm[kMaxDims];
 #pragma unroll
                 for (int a = 0; a < kMaxDims; ++a)
@@ -380,19 +390,39 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
                 stats_add_rt(st, xm, take ? w[j] : 0.0, M.dims);
             }
             double *lst = reinterpret_cast<double *>(smem + M.lds_stats);
+            uint32_t *lcnt = reinterpret_cast<uint32_t *>(lst + kMaxStats);
+            if ((tid & (kWave - 1)) == 0) {
+                if (nkept)
+                    lds_add_u32(&lcnt[0], nkept);
+                if (nin)
+                    lds_add_u32(&lcnt[1], nin);
+            }
+            const int s0 = weighted ? 0 : 2;   // unit weights: w and w^2 are the count
+            if (M.lds_tstats >= 0) {
+                double *ts = reinterpret_cast<double *>(smem + M.lds_tstats) + tid;
 #pragma unroll
-            for (int s = 0; s < kMaxStats; ++s)
-                if (s < M.nstats)
-                    wave_add_lds(st[s], &lst[s]);
-            {
-                uint32_t v = kept;
+                for (int s = 0; s < kMaxStats; ++s)
+                    if (s >= s0 && s < M.nstats)
+                        ts[(s - s0) * nthr] += st[s];
+            } else {
 #pragma unroll
-                for (int off = kWave / 2; off > 0; off >>= 1)
-                    v += __shfl_xor(v, off, kWave);
-                if ((tid & (kWave - 1)) == 0 && v)
-                    lds_add_u32(reinterpret_cast<uint32_t *>(lst + kMaxStats), v);
+                for (int s = 0; s < kMaxStats; ++s)
+                    if (s >= s0 && s < M.nstats)
+                        wave_add_lds(st[s], &lst[s]);
             }
         }
+    }
+    __syncthreads();
+    // per-thread sums -> the member's statistics partials (once per block)
+    for (int m = 0; m < A.k; ++m) {
+        const MultiMember &M = *(const MultiMember *)&mem[m];
+        if (M.lds_tstats < 0)
+            continue;
+        const double *ts = reinterpret_cast<const double *>(smem + M.lds_tstats);
+        double *lst = reinterpret_cast<double *>(smem + M.lds_stats);
+        const int s0 = M.weight.nops > 0 ? 0 : 2;
+        for (int s = s0; s < M.nstats; ++s)
+            wave_add_lds(ts[(s - s0) * nthr + tid], &lst[s]);
     }
     __syncthreads();
 
@@ -428,13 +458,14 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
             }
         }
         const double *lst = reinterpret_cast<const double *>(smem + M.lds_stats);
-        if (tid < M.nstats && lst[tid] != 0.0)
+        const uint32_t *lcnt = reinterpret_cast<const uint32_t *>(lst + kMaxStats);
+        const int s0 = weighted ? 0 : 2;
+        if (tid >= s0 && tid < M.nstats && lst[tid] != 0.0)
             gl_add_f64(&M.stats[tid], lst[tid]);
-        if (tid == nthr - 1) {
-            const uint32_t kept = *reinterpret_cast<const uint32_t *>(lst + kMaxStats);
-            if (kept)
-                gl_add_u64(M.entries, kept);
-        }
+        if (!weighted && tid < 2 && lcnt[1])
+            gl_add_f64(&M.stats[tid], (double)lcnt[1]);
+        if (tid == nthr - 1 && lcnt[0])
+            gl_add_u64(M.entries, lcnt[0]);
     }
 }
 
@@ -599,6 +630,8 @@ extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_de
         d.entries = h->d_entries;
         d.lds_win = -1;
         d.copies = 1;
+        d.lds_tstats = -1;
+        d.nsums = d.weight.nops > 0 ? h->S : h->S - 2;
     }
 
     // LDS: statistics of every member, then learned models (a learned axis
@@ -631,40 +664,51 @@ extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_de
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return M->members[a].total_bins < M->members[b].total_bins; });
     auto bin_bytes = [&](const MultiMember &d) { return d.weight.nops > 0 ? 16 : 4; };
+    auto up16 = [](int64_t x) { return (x + 15) & ~(int64_t)15; };
+    // 1. whole-histogram windows (one copy), smallest histograms first
+    int64_t win_total = 0;
     for (int i : order) {
-        MultiMember &d = M->members[i];
-        const int64_t need = (int64_t)d.total_bins * bin_bytes(d);
-        if (off + need <= lds_max) {
-            d.lds_win = off;
-            off = (int)((off + need + 15) & ~(int64_t)15);
+        const MultiMember &d = M->members[i];
+        const int64_t need = up16((int64_t)d.total_bins * bin_bytes(d));
+        if (off + win_total + need <= lds_max) {
+            win_total += need;
             M->window_members.push_back(i);
         }
     }
-    // interleaved copies with the LDS left, so lanes of a wave that hit one
-    // bin of a small histogram update different words
-    for (int copies = 2; copies <= 16; copies *= 2) {
-        int64_t extra = 0;
-        for (int i : M->window_members) {
-            const MultiMember &d = M->members[i];
-            extra += (int64_t)d.total_bins * bin_bytes(d) * (copies - d.copies);
+    // 2. per-thread statistics sums, in member order, with the LDS left; the
+    //    others reduce per wave and event slot (far slower)
+    int64_t ts_total = 0;
+    std::vector<int> ts_members;
+    for (int i = 0; i < k; ++i) {
+        const MultiMember &d = M->members[i];
+        const int64_t need = up16((int64_t)d.nsums * kMaxThreads * 8);
+        if (d.nsums > 0 && off + win_total + ts_total + need <= lds_max) {
+            ts_total += need;
+            ts_members.push_back(i);
         }
-        if (M->window_members.empty() || off + extra > lds_max)
+    }
+    // 3. interleaved copies of the windows with what is left (up to 16), so
+    //    lanes of a wave that hit one bin of a small histogram update
+    //    different words
+    int copies = 1;
+    while (copies < 16 && !M->window_members.empty()) {
+        int64_t w2 = 0;
+        for (int i : M->window_members)
+            w2 += up16((int64_t)M->members[i].total_bins * bin_bytes(M->members[i]) * copies * 2);
+        if (off + w2 + ts_total > lds_max)
             break;
-        // re-lay the windows with `copies` copies each
-        int o2 = k * kMultiStatsBytes;
-        for (int i = 0; i < k; ++i)
-            for (int a = 0; a < M->members[i].dims; ++a) {
-                const AxisDev &ax = M->members[i].ax[a];
-                if (ax.lds_edges >= 0)
-                    o2 = std::max(o2, ax.lds_edges + (((ax.nbins + 1) * 8 + 15) & ~15));
-            }
-        for (int i : M->window_members) {
-            MultiMember &d = M->members[i];
-            d.copies = copies;
-            d.lds_win = o2;
-            o2 = (int)((o2 + (int64_t)d.total_bins * bin_bytes(d) * copies + 15) & ~(int64_t)15);
-        }
-        off = o2;
+        copies *= 2;
+    }
+    for (int i : M->window_members) {
+        MultiMember &d = M->members[i];
+        d.copies = copies;
+        d.lds_win = off;
+        off = (int)(off + up16((int64_t)d.total_bins * bin_bytes(d) * copies));
+    }
+    for (int i : ts_members) {
+        MultiMember &d = M->members[i];
+        d.lds_tstats = off;
+        off = (int)(off + up16((int64_t)d.nsums * kMaxThreads * 8));
     }
     M->lds = std::max(off, 16);
 
