@@ -215,9 +215,9 @@ __device__ __forceinline__ void member_axis_bins(const double (&x)[U], const Axi
 }
 
 template <typename T>
-__device__ __forceinline__ double load_col(const void *p, int64_t i)
+__device__ __forceinline__ T load_col(const void *p, int64_t i)
 {
-    return (double)__builtin_nontemporal_load(static_cast<const T *>(p) + i);
+    return __builtin_nontemporal_load(static_cast<const T *>(p) + i);
 }
 
 // Wave sum of a double, then one LDS atomic by the wave's first lane.
@@ -277,21 +277,34 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
         for (int j = 0; j < U; ++j)
             r[s][j] = 0.0;
 
+    // every column of a batch is read once, for all members; the next batch
+    // is requested before the current one is processed
+    T nv[NC][U];
+    auto load_batch = [&](int64_t b) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int64_t i = b + (int64_t)j * nthr + tid;
+                nv[c][j] = (c < A.ncols && i < end) ? load_col<T>(A.cols[c], i) : T(0);
+            }
+        }
+    };
+    if (start < end)
+        load_batch(start);
     for (int64_t base = start; base < end; base += (int64_t)nthr * U) {
         double cv[NC][U];
         bool ok[U];
 #pragma unroll
         for (int j = 0; j < U; ++j)
             ok[j] = base + (int64_t)j * nthr + tid < end;
-        // every column of the batch is read once, for all members
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const int64_t i = base + (int64_t)j * nthr + tid;
-                cv[c][j] = (c < A.ncols && ok[j]) ? load_col<T>(A.cols[c], i) : 0.0;
-            }
-        }
+            for (int j = 0; j < U; ++j)
+                cv[c][j] = (double)nv[c][j];
+        if (base + (int64_t)nthr * U < end)
+            load_batch(base + (int64_t)nthr * U);
         for (int m = 0; m < A.k; ++m) {
             const MultiMember &M = *(const MultiMember *)&mem[m];
             bool keep[U];
