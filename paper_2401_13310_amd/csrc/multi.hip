@@ -32,7 +32,7 @@ namespace hg {
 
 constexpr int kMultiMembers = 16;
 constexpr int kMultiCols = 8;
-constexpr int kExprStack = 6;
+constexpr int kExprStack = 6;       // at most 8 (one vector of registers)
 constexpr int kExprMaxOps = 32;
 constexpr int kMultiU = 1;           // events per thread per batch
 constexpr int kMultiStatsBytes = 96; // per member: kMaxStats doubles, kept and in-range counts
@@ -85,58 +85,36 @@ struct MultiArgs {
 
 __device__ __forceinline__ double truth(bool b) { return b ? 1.0 : 0.0; }
 
-// One operation at stack depth SP on U events.  Binary operations take the
-// two top slots and leave the result in the lower one; SELECT (c, a, b) keeps
-// a where c is nonzero, else b.
-template <int SP, int NC, int U>
-__device__ __forceinline__ void expr_step(const ExprOp &op, double (&r)[kExprStack][U],
-                                          const double (&cv)[NC][U])
+// Programs run on one event per lane with the stack held in registers as one
+// vector: every operation reads its operands and writes its result at the
+// (uniform) stack depth the host recorded, i.e. an indexed register move
+// each, so the operation's own code is the only thing the dispatch selects.
+using dvec8 = double __attribute__((ext_vector_type(8)));
+
+template <int NC>
+__device__ __forceinline__ double run_expr(ConstExprOp *ops, ExprRef e, dvec8 &stk, const dvec8 &cv)
 {
 #pragma clang fp contract(off)
-    const int code = op.code;
-    if (code == HIST_OP_COL || code == HIST_OP_CONST) {
-        if constexpr (SP < kExprStack) {
-            if (code == HIST_OP_CONST) {
-#pragma unroll
-                for (int j = 0; j < U; ++j)
-                    r[SP][j] = op.value;
-            } else {
-#pragma unroll
-                for (int c = 0; c < NC; ++c)
-                    if (op.col == c) {
-#pragma unroll
-                        for (int j = 0; j < U; ++j)
-                            r[SP][j] = cv[c][j];
-                    }
-            }
-        }
-        return;
-    }
-    if (code == HIST_OP_NEG || code == HIST_OP_ABS || code == HIST_OP_SQRT || code == HIST_OP_NOT) {
-        if constexpr (SP >= 1) {
-#pragma unroll
-            for (int j = 0; j < U; ++j) {
-                const double a = r[SP - 1][j];
-                r[SP - 1][j] = code == HIST_OP_NEG   ? -a
-                               : code == HIST_OP_ABS ? __builtin_fabs(a)
-                               : code == HIST_OP_NOT ? truth(a == 0.0)
-                                                     : __builtin_sqrt(a);
-            }
-        }
-        return;
-    }
-    if (code == HIST_OP_SELECT) {
-        if constexpr (SP >= 3) {
-#pragma unroll
-            for (int j = 0; j < U; ++j)
-                r[SP - 3][j] = r[SP - 3][j] != 0.0 ? r[SP - 2][j] : r[SP - 1][j];
-        }
-        return;
-    }
-    if constexpr (SP >= 2) {
-#pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const double a = r[SP - 2][j], b = r[SP - 1][j];
+    for (int pc = 0; pc < e.nops; ++pc) {
+        const ExprOp op = *(const ExprOp *)&ops[e.first + pc];
+        const int sp = op.sp;
+        const int code = op.code;
+        if (code == HIST_OP_CONST) {
+            stk[sp] = op.value;
+        } else if (code == HIST_OP_COL) {
+            stk[sp] = cv[op.col];
+        } else if (code == HIST_OP_NEG || code == HIST_OP_ABS || code == HIST_OP_SQRT ||
+                   code == HIST_OP_NOT) {
+            const double a = stk[sp - 1];
+            stk[sp - 1] = code == HIST_OP_NEG   ? -a
+                          : code == HIST_OP_ABS ? __builtin_fabs(a)
+                          : code == HIST_OP_NOT ? truth(a == 0.0)
+                                                : __builtin_sqrt(a);
+        } else if (code == HIST_OP_SELECT) {
+            const double c = stk[sp - 3], a = stk[sp - 2], b = stk[sp - 1];
+            stk[sp - 3] = c != 0.0 ? a : b;
+        } else {
+            const double a = stk[sp - 2], b = stk[sp - 1];
             double v;
             switch (code) {
             case HIST_OP_ADD: v = a + b; break;
@@ -154,32 +132,10 @@ __device__ __forceinline__ void expr_step(const ExprOp &op, double (&r)[kExprSta
             case HIST_OP_AND: v = truth(a != 0.0 && b != 0.0); break;
             default: v = truth(a != 0.0 || b != 0.0); break;   // HIST_OP_OR
             }
-            r[SP - 2][j] = v;
+            stk[sp - 2] = v;
         }
     }
-}
-
-// Runs a program on U events; the result is the bottom stack slot.  `r` is
-// the caller's register stack (initialized once, reused by every program).
-template <int NC, int U>
-__device__ __forceinline__ void run_expr(ConstExprOp *ops, ExprRef e, double (&r)[kExprStack][U],
-                                         const double (&cv)[NC][U], double (&out)[U])
-{
-    for (int pc = 0; pc < e.nops; ++pc) {
-        const ExprOp op = *(const ExprOp *)&ops[e.first + pc];
-        switch (op.sp) {
-        case 0: expr_step<0, NC, U>(op, r, cv); break;
-        case 1: expr_step<1, NC, U>(op, r, cv); break;
-        case 2: expr_step<2, NC, U>(op, r, cv); break;
-        case 3: expr_step<3, NC, U>(op, r, cv); break;
-        case 4: expr_step<4, NC, U>(op, r, cv); break;
-        case 5: expr_step<5, NC, U>(op, r, cv); break;
-        default: expr_step<6, NC, U>(op, r, cv); break;
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < U; ++j)
-        out[j] = r[0][j];
+    return stk[0];
 }
 
 // ------------------------------------------------------------------ kernel --
@@ -270,12 +226,9 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
 
     const int64_t start = (int64_t)blockIdx.x * A.per_block;
     const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
-    double r[kExprStack][U];
-#pragma unroll
-    for (int s = 0; s < kExprStack; ++s)
-#pragma unroll
-        for (int j = 0; j < U; ++j)
-            r[s][j] = 0.0;
+    static_assert(U == 1, "programs run on one event per lane");
+    static_assert(kExprStack <= 8 && NC <= 8, "stack and columns fit one 8-wide vector");
+    dvec8 stk = 0.0;
 
     // every column of a batch is read once, for all members; the next batch
     // is requested before the current one is processed
@@ -293,16 +246,14 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
     if (start < end)
         load_batch(start);
     for (int64_t base = start; base < end; base += (int64_t)nthr * U) {
-        double cv[NC][U];
+        dvec8 cv = 0.0;
         bool ok[U];
 #pragma unroll
         for (int j = 0; j < U; ++j)
             ok[j] = base + (int64_t)j * nthr + tid < end;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int j = 0; j < U; ++j)
-                cv[c][j] = (double)nv[c][j];
+            cv[c] = (double)nv[c][0];
         if (base + (int64_t)nthr * U < end)
             load_batch(base + (int64_t)nthr * U);
         for (int m = 0; m < A.k; ++m) {
@@ -311,7 +262,7 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
             {
                 double f[U];
                 if (M.filter.nops > 0) {
-                    run_expr<NC, U>(ops, M.filter, r, cv, f);
+                    f[0] = run_expr<NC>(ops, M.filter, stk, cv);
 #pragma unroll
                     for (int j = 0; j < U; ++j)
                         keep[j] = ok[j] && f[j] != 0.0;
@@ -324,18 +275,15 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
             double x[kMaxDims][U];
 #pragma unroll
             for (int a = 0; a < kMaxDims; ++a) {
-                if (a < M.dims && M.coord[a].nops > 0) {
-                    run_expr<NC, U>(ops, M.coord[a], r, cv, x[a]);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < U; ++j)
-                        x[a][j] = a < NC ? cv[a < NC ? a : 0][j] : 0.0;
-                }
+                if (a < M.dims && M.coord[a].nops > 0)
+                    x[a][0] = run_expr<NC>(ops, M.coord[a], stk, cv);
+                else
+                    x[a][0] = a < NC ? cv[a] : 0.0;
             }
             const bool weighted = M.weight.nops > 0;
             double w[U];
             if (weighted) {
-                run_expr<NC, U>(ops, M.weight, r, cv, w);
+                w[0] = run_expr<NC>(ops, M.weight, stk, cv);
             } else {
 #pragma unroll
                 for (int j = 0; j < U; ++j)
