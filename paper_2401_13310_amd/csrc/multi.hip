@@ -61,6 +61,9 @@ struct MultiMember {
     int32_t nsums;        // sums per event: all statistics (weighted) or all but the counts
     int32_t total_bins;
     ExprRef filter, coord[kMaxDims], weight;
+    int32_t coord_col[kMaxDims];   // coordinate read straight from this column, -1: program
+    int32_t weight_col;            // weight column, -1: program or unit weights
+    int32_t weighted;              // a weight program or column
     uint64_t *cnt;
     double *sumw, *sumw2, *stats;
     uint64_t *entries;
@@ -140,6 +143,32 @@ __device__ __forceinline__ double run_expr(ConstExprOp *ops, ExprRef e, dvec8 &s
 
 // ------------------------------------------------------------------ kernel --
 
+// Statistics terms of one event of a member with `dims` axes, in the order of
+// the statistics array (every index fixed at compile time).
+__device__ __forceinline__ void member_stats_add(double (&st)[kMaxStats], const double (&x)[kMaxDims],
+                                                 double w, int dims)
+{
+#pragma clang fp contract(off)
+    st[0] += w;
+    st[1] += w * w;
+    const double w0 = w * x[0];
+    st[2] += w0;
+    st[3] += w0 * x[0];
+    if (dims > 1) {
+        const double w1 = w * x[1];
+        st[4] += w1;
+        st[5] += w1 * x[1];
+        st[6] += w0 * x[1];
+        if (dims > 2) {
+            const double w2 = w * x[2];
+            st[7] += w2;
+            st[8] += w2 * x[2];
+            st[9] += w0 * x[2];
+            st[10] += w1 * x[2];
+        }
+    }
+}
+
 // Bins of U coordinates on one axis of a member: the fixed-width formula, or
 // a binary search over the edges (staged in LDS when the plan put them
 // there).  Learned indexes are not used in these passes: the plan turns such
@@ -217,7 +246,7 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
         }
         if (M.lds_win >= 0) {
             uint32_t *win = reinterpret_cast<uint32_t *>(smem + M.lds_win);
-            const int words = M.total_bins * M.copies * (M.weight.nops > 0 ? 4 : 1);
+            const int words = M.total_bins * M.copies * (M.weighted ? 4 : 1);
             for (int i = tid; i < words; i += nthr)
                 win[i] = 0u;
         }
@@ -278,12 +307,14 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
                 if (a < M.dims && M.coord[a].nops > 0)
                     x[a][0] = run_expr<NC>(ops, M.coord[a], stk, cv);
                 else
-                    x[a][0] = a < NC ? cv[a] : 0.0;
+                    x[a][0] = a < M.dims ? cv[M.coord_col[a]] : 0.0;
             }
-            const bool weighted = M.weight.nops > 0;
+            const bool weighted = M.weighted != 0;
             double w[U];
-            if (weighted) {
+            if (M.weight.nops > 0) {
                 w[0] = run_expr<NC>(ops, M.weight, stk, cv);
+            } else if (weighted) {
+                w[0] = cv[M.weight_col];
             } else {
 #pragma unroll
                 for (int j = 0; j < U; ++j)
@@ -348,7 +379,7 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
 #pragma unroll
                 for (int a = 0; a < kMaxDims; ++a)
                     xm[a] = take ? x[a][j] : 0.0;
-                stats_add_rt(st, xm, take ? w[j] : 0.0, M.dims);
+                member_stats_add(st, xm, take ? w[j] : 0.0, M.dims);
             }
             double *lst = reinterpret_cast<double *>(smem + M.lds_stats);
             uint32_t *lcnt = reinterpret_cast<uint32_t *>(lst + kMaxStats);
@@ -381,7 +412,7 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
             continue;
         const double *ts = reinterpret_cast<const double *>(smem + M.lds_tstats);
         double *lst = reinterpret_cast<double *>(smem + M.lds_stats);
-        const int s0 = M.weight.nops > 0 ? 0 : 2;
+        const int s0 = M.weighted ? 0 : 2;
         for (int s = s0; s < M.nstats; ++s)
             wave_add_lds(ts[(s - s0) * nthr + tid], &lst[s]);
     }
@@ -390,7 +421,7 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
     // merge: LDS copies into the member histograms, statistics, kept counts
     for (int m = 0; m < A.k; ++m) {
         const MultiMember &M = *(const MultiMember *)&mem[m];
-        const bool weighted = M.weight.nops > 0;
+        const bool weighted = M.weighted != 0;
         if (M.lds_win >= 0) {
             const int C = M.copies;
             if (weighted) {
@@ -569,6 +600,20 @@ extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_de
             free_multi(M);
             return st;
         }
+        // a program that only reads a column is read directly
+        for (int a = 0; a < kMaxDims; ++a) {
+            d.coord_col[a] = a < h->dims && a < ncols ? a : 0;
+            if (d.coord[a].nops == 1 && def.coord[a].ops[0].op == HIST_OP_COL) {
+                d.coord_col[a] = def.coord[a].ops[0].col;
+                d.coord[a].nops = 0;
+            }
+        }
+        d.weighted = d.weight.nops > 0 ? 1 : 0;
+        d.weight_col = -1;
+        if (d.weight.nops == 1 && def.weight.ops[0].op == HIST_OP_COL) {
+            d.weight_col = def.weight.ops[0].col;
+            d.weight.nops = 0;
+        }
         for (int a = 0; a < h->dims; ++a) {
             if (def.coord[a].nops == 0 && a >= ncols) {
                 free_multi(M);
@@ -592,7 +637,7 @@ extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_de
         d.lds_win = -1;
         d.copies = 1;
         d.lds_tstats = -1;
-        d.nsums = d.weight.nops > 0 ? h->S : h->S - 2;
+        d.nsums = d.weighted ? h->S : h->S - 2;
     }
 
     // LDS: statistics of every member, then learned models (a learned axis
@@ -624,7 +669,7 @@ extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_de
         order[i] = i;
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return M->members[a].total_bins < M->members[b].total_bins; });
-    auto bin_bytes = [&](const MultiMember &d) { return d.weight.nops > 0 ? 16 : 4; };
+    auto bin_bytes = [&](const MultiMember &d) { return d.weighted ? 16 : 4; };
     auto up16 = [](int64_t x) { return (x + 15) & ~(int64_t)15; };
     // 1. whole-histogram windows (one copy), smallest histograms first
     int64_t win_total = 0;
