@@ -64,6 +64,8 @@ struct MultiMember {
     int32_t coord_col[kMaxDims];   // coordinate read straight from this column, -1: program
     int32_t weight_col;            // weight column, -1: program or unit weights
     int32_t weighted;              // a weight program or column
+    int32_t lean;                  // one fixed-width axis read from a column, unit weights, no
+                                   // filter, LDS copy and per-thread sums: the short path
     uint64_t *cnt;
     double *sumw, *sumw2, *stats;
     uint64_t *entries;
@@ -287,6 +289,32 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
             load_batch(base + (int64_t)nthr * U);
         for (int m = 0; m < A.k; ++m) {
             const MultiMember &M = *(const MultiMember *)&mem[m];
+            if (M.lean) {
+                // a plain projection: bin, count in LDS, sums of x and x^2
+                const double xs[1] = {cv[M.coord_col[0]]};
+                int32_t b[1];
+                bool inr[1];
+                bins_uniform<1>(xs, M.ax[0], b, inr);
+                if (ok[0])
+                    lds_add_u32(reinterpret_cast<uint32_t *>(smem + M.lds_win) +
+                                    ((uint32_t)b[0] * (uint32_t)M.copies + (uint32_t)(tid % M.copies)), 1u);
+                const bool take = ok[0] && inr[0];
+                const uint32_t nk = (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(ok[0]));
+                const uint32_t ni = (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(take));
+                if ((tid & (kWave - 1)) == 0) {
+                    uint32_t *lcnt = reinterpret_cast<uint32_t *>(
+                        reinterpret_cast<double *>(smem + M.lds_stats) + kMaxStats);
+                    if (nk)
+                        lds_add_u32(&lcnt[0], nk);
+                    if (ni)
+                        lds_add_u32(&lcnt[1], ni);
+                }
+                const double xm = take ? xs[0] : 0.0;
+                double *ts = reinterpret_cast<double *>(smem + M.lds_tstats) + tid;
+                ts[0] += xm;
+                ts[nthr] += xm * xm;
+                continue;
+            }
             bool keep[U];
             {
                 double f[U];
@@ -715,6 +743,11 @@ extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_de
         MultiMember &d = M->members[i];
         d.lds_tstats = off;
         off = (int)(off + up16((int64_t)d.nsums * kMaxThreads * 8));
+    }
+    for (int i = 0; i < k; ++i) {
+        MultiMember &d = M->members[i];
+        d.lean = d.dims == 1 && d.ax[0].kind == AX_UNIFORM && d.filter.nops == 0 &&
+                 d.coord[0].nops == 0 && !d.weighted && d.lds_win >= 0 && d.lds_tstats >= 0;
     }
     M->lds = std::max(off, 16);
 
