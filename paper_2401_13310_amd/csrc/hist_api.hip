@@ -374,6 +374,57 @@ static PartLayout part_layout(const hist_s *h, const Plan &p, int64_t mmax, bool
 // part_chunk events (see partition.hip).
 static size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// The learned one-axis kernel: one binary64 axis with a trained index whose
+// edges stay in HBM, unit weights, 16-bit LDS window, the heuristic shape.
+static bool use_learned_lean(const hist_s *h, const Plan &p, bool f32, bool weighted)
+{
+    return p.strategy == HIST_STRAT_LDS && !p.shape && p.unroll == 8 &&
+           learned_lean_supported(h->dims, f32, weighted, p.acc, h->ax);
+}
+
+// Records of its per-workgroup list of events with several candidate bins:
+// about one in 24 events of a workgroup (the learned index leaves a few per
+// cent), at most one 16-bit counter epoch.
+static int32_t lean_rare_cap(const Plan &p)
+{
+    int64_t cap = p.per_block / 24;
+    cap = std::max<int64_t>(cap, 1024);
+    cap = std::min<int64_t>(cap, kU16EpochEvents);
+    return (int32_t)cap;
+}
+
+static size_t lean_rare_bytes(const Plan &p)
+{
+    return (size_t)p.blocks * (size_t)lean_rare_cap(p) * sizeof(uint4);
+}
+
+// Its LDS layout: the window at 0, the model, the statistics partials and the
+// list count, the hot-bin cache; the window gives up bins (a few, from its top)
+// if the LDS would be exceeded.  Returns the LDS bytes, 0 if no window fits.
+static int lean_layout(const hist_s *h, const Plan &p, FillArgs &a)
+{
+    auto a16 = [](int64_t x) { return (x + 15) & ~(int64_t)15; };
+    const int64_t model_b = (int64_t)h->ax[0].nseg * (int64_t)sizeof(ModelSeg);
+    const int64_t cache_b = p.lds_cache >= 0 ? cache_bytes(p.cache_slots, false) : 0;
+    int64_t wl = p.win_len, total = 0;
+    for (;;) {
+        total = a16(((wl + 1) / 2) * 4) + a16(model_b) + kRedBytes + 16 + cache_b;
+        if (total <= h->lds_max)
+            break;
+        wl -= 64;
+        if (wl < 64)
+            return 0;
+    }
+    const int64_t win_b = a16(((wl + 1) / 2) * 4);
+    a.win_len = (int32_t)wl;
+    a.lds_win = 0;
+    a.ax[0].lds_model = (int32_t)win_b;
+    a.lds_red = (int32_t)(win_b + a16(model_b));
+    a.lds_cache = p.lds_cache >= 0 ? a.lds_red + kRedBytes + 16 : -1;
+    a.rare_cap = lean_rare_cap(p);
+    return (int)total;
+}
+
 // Events per chunk of a partitioned fill whose scratch (bin array plus
 // partition tables) must fit `bytes`: the largest power of two up to the
 // usual chunk that fits, 0 if none of at least 2^12 does.
@@ -667,20 +718,37 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
     a.cache_slots = p.cache_slots;
     a.epoch_iters = p.epoch_iters;
     a.per_block = p.per_block;
-    if (p.merge == MERGE_STAGE) {
+    const bool lean = use_learned_lean(h, p, f32, weighted);
+    const int lean_lds = lean ? lean_layout(h, p, a) : 0;
+    if (lean && lean_lds <= 0)
+        return set_error(HIST_EINVAL, "hist_fill: no LDS layout for the learned kernel");
+    if (p.merge == MERGE_STAGE || lean) {
+        // staging slots (staged merge), then the learned kernel's lists
+        const size_t stage_b = p.merge == MERGE_STAGE ? stage_bytes_for(p) : 0;
+        const size_t want = up256(stage_b) + (lean ? lean_rare_bytes(p) : 0);
+        char *base = nullptr;
         if (fx) {
-            if (stage_bytes_for(p) > fx->bytes)
+            if (stage_b > fx->bytes)
                 return set_error(HIST_ENOMEM, "hist_fill_static: the staging slots of this plan (%zu "
                                               "bytes) exceed the %zu-byte scratch",
-                                 stage_bytes_for(p), fx->bytes);
-            a.stage = fx->base;
+                                 stage_b, fx->bytes);
+            base = fx->base;
+            if (lean) {
+                // the lists take what the region has left (a full list is
+                // searched in place)
+                const size_t room = (fx->bytes - up256(stage_b)) / ((size_t)p.blocks * sizeof(uint4));
+                a.rare_cap = (int32_t)std::min<size_t>((size_t)a.rare_cap, room);
+            }
         } else {
-            hist_status st = ensure_stage(h, stage_bytes_for(p), s);
+            hist_status st = ensure_stage(h, want, s);
             if (st != HIST_OK)
                 return st;
-            a.stage = h->d_stage;
+            base = static_cast<char *>(h->d_stage);
         }
-        a.stage_stride = stage_stride_for(p);
+        a.stage = base;
+        a.stage_stride = p.acc == ACC_U16 ? (a.win_len + 1) / 2 : a.win_len;
+        if (lean)
+            a.rare = reinterpret_cast<uint4 *>(base + up256(stage_b));
     }
     const int t0 = h->timing ? timing_event(h) : -1;
     if (t0 >= 0)
@@ -691,6 +759,8 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
                "fill launch");
         if (p.stats_ept > 0)
             HIPCHK(launch_stats_separate(weighted, p.stats_ept, h->num_cu, a, s), "statistics launch");
+    } else if (lean) {
+        HIPCHK(launch_fill_learned(p.threads, p.blocks, (size_t)lean_lds, a, s), "fill launch");
     } else {
         HIPCHK(launch_fill(h->dims, f32, p.acc, weighted, p.threads, p.blocks, (size_t)p.lds, a, s),
                "fill launch");
@@ -809,8 +879,11 @@ hist_status hg::reserve_scratch(hist_s *h, int64_t n_max, hist_dtype dtype, bool
     // plan of n_max events bounds every smaller fill.
     const Plan p = make_plan(h, n_max, dtype, weighted);
     hist_status st = HIST_OK;
-    if (p.strategy == HIST_STRAT_LDS && p.merge == MERGE_STAGE)
-        st = ensure_stage(h, stage_bytes_for(p), s, true);
+    const bool lean = use_learned_lean(h, p, dtype == HIST_F32, weighted);
+    if (p.strategy == HIST_STRAT_LDS && (p.merge == MERGE_STAGE || lean))
+        st = ensure_stage(h, (p.merge == MERGE_STAGE ? up256(stage_bytes_for(p)) : 0) +
+                                 (lean ? lean_rare_bytes(p) : 0),
+                          s, true);
     if (st == HIST_OK && p.strategy == HIST_STRAT_TILED)
         st = ensure_gbins(h, std::min<int64_t>(n_max, tiled_chunk(h)), s, true);
     if (st == HIST_OK && p.strategy == HIST_STRAT_PART) {
