@@ -82,7 +82,12 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
     // rare-list counter and the hot-bin cache (offsets from the host)
     uint32_t *win = reinterpret_cast<uint32_t *>(smem);
     const ModelSeg *model = reinterpret_cast<const ModelSeg *>(smem + ax.lds_model);
-    uint32_t *rare_n = reinterpret_cast<uint32_t *>(smem + A.lds_red + kRedBytes);   // list count
+    // the list of a workgroup is cut into one region per wave, filled with a
+    // wave-private (scalar) count: no atomics; the counts go to LDS at the end
+    uint32_t *rare_n = reinterpret_cast<uint32_t *>(smem + A.lds_red + kRedBytes);
+    const int nwaves = nthr / kWave;
+    const uint32_t wcap = (uint32_t)A.rare_cap / (uint32_t)nwaves;
+    const int wave = tid / kWave;
     {
         // the model, with the window's first bin subtracted from its offsets
         ModelSeg *dst = reinterpret_cast<ModelSeg *>(smem + ax.lds_model);
@@ -94,8 +99,6 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
         const int words = (A.win_len + 1) >> 1;
         for (int i = tid; i < words; i += nthr)
             win[i] = 0u;
-        if (tid == 0)
-            *rare_n = 0u;
     }
     cache_init<false>(A, smem);
     __syncthreads();
@@ -113,6 +116,7 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
 
     double sx = 0.0, sxx = 0.0;
     uint32_t nok = 0, nflow = 0;   // events of this thread, and those out of range
+    uint32_t wcount = 0;           // records this wave has listed (wave-uniform)
     int it = 0;
     // full batches need no per-event range check; the block's partial last
     // batch runs the same body with one
@@ -174,20 +178,17 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
             const bool rare_ev = ok && in && !one;
             const uint64_t rmask = __builtin_amdgcn_ballot_w64(rare_ev);
             if (rmask) {
-                uint32_t first = 0;
-                if (lane == 0)
-                    first = __hip_atomic_fetch_add(rare_n, (uint32_t)__builtin_popcountll(rmask),
-                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                first = __builtin_amdgcn_readfirstlane(first);
+                const uint32_t first = wcount;
+                wcount += (uint32_t)__builtin_popcountll(rmask);
                 if (rare_ev) {
                     const uint32_t idx =
                         first + __builtin_amdgcn_mbcnt_hi((uint32_t)(rmask >> 32),
                                                           __builtin_amdgcn_mbcnt_lo((uint32_t)rmask, 0u));
                     const int32_t lo = a + A.win_lo, h = b + A.win_lo;
-                    if (idx < (uint32_t)A.rare_cap) {
+                    if (idx < wcap) {
                         const uint64_t xb64 = (uint64_t)__double_as_longlong(x[j]);
-                        rare[idx] = make_uint4((uint32_t)xb64, (uint32_t)(xb64 >> 32), (uint32_t)lo,
-                                               (uint32_t)h);
+                        rare[wave * wcap + idx] = make_uint4((uint32_t)xb64, (uint32_t)(xb64 >> 32),
+                                                             (uint32_t)lo, (uint32_t)h);
                     } else {
                         // the list is full: search here
                         lean_search_add(A, smem, win, x[j], lo, h);
@@ -215,15 +216,54 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
         iteration(base, std::false_type{});
 
     // resolve the listed events: counters drained first, so the at most
-    // rare_cap (<= kU16EpochEvents) increments cannot overflow them
+    // rare_cap (<= kU16EpochEvents) increments cannot overflow them.  Eight
+    // records per thread at a time, their first edge reads issued together.
+    if (lane == 0)
+        rare_n[wave] = wcount < wcap ? wcount : wcap;
     __syncthreads();
     drain_u16(win, (A.win_len + 1) >> 1, A.win_lo, A.cnt);
     __syncthreads();
-    const uint32_t nlist = __builtin_elementwise_min(*rare_n, (uint32_t)A.rare_cap);
-    for (uint32_t i = tid; i < nlist; i += nthr) {
-        const uint4 r = rare[i];
-        const double xv = __longlong_as_double((int64_t)(((uint64_t)r.y << 32) | r.x));
-        lean_search_add(A, smem, win, xv, (int32_t)r.z, (int32_t)r.w);
+    {
+        constexpr int R = 8;
+        const uint32_t total = (uint32_t)nwaves * wcap;
+        for (uint32_t c = 0; c < total; c += (uint32_t)nthr * R) {
+            double xv[R], ev[R];
+            int32_t lo[R], hi[R];
+            bool valid[R];
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const uint32_t i = c + (uint32_t)j * nthr + tid;
+                valid[j] = i < total && wcap > 0 && i % wcap < rare_n[i / wcap];
+                uint4 r = make_uint4(0u, 0u, 1u, 0u);
+                if (valid[j])
+                    r = rare[i];
+                xv[j] = __longlong_as_double((int64_t)(((uint64_t)r.y << 32) | r.x));
+                lo[j] = (int32_t)r.z;
+                hi[j] = (int32_t)r.w;
+                if (lo[j] > hi[j]) {   // an interval the model could not bound: the whole axis
+                    lo[j] = 1;
+                    hi[j] = ax.nbins;
+                }
+            }
+            first_step_loads<R>(ax.edges, ax.nbins, lo, hi, ev);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if (lo[j] < hi[j]) {
+                    const int32_t mid = (lo[j] + hi[j] + 1) >> 1;
+                    if (!(xv[j] < ev[j]))
+                        lo[j] = mid;
+                    else
+                        hi[j] = mid - 1;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                if (valid[j]) {
+                    search_one(xv[j], ax.edges, ax.nbins, lo[j], hi[j]);
+                    lean_add(A, smem, win, lo[j]);
+                }
+            }
+        }
     }
 
     const double nin = (double)(nok - nflow);

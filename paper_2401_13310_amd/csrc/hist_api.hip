@@ -382,12 +382,12 @@ static bool use_learned_lean(const hist_s *h, const Plan &p, bool f32, bool weig
            learned_lean_supported(h->dims, f32, weighted, p.acc, h->ax);
 }
 
-// Records of its per-workgroup list of events with several candidate bins:
-// about one in 24 events of a workgroup (the learned index leaves a few per
-// cent), at most one 16-bit counter epoch.
+// Records of its per-workgroup list of events with several candidate bins
+// (one region per wave): about one in 16 events of a workgroup (the learned
+// index leaves a few per cent), at most one 16-bit counter epoch.
 static int32_t lean_rare_cap(const Plan &p)
 {
-    int64_t cap = p.per_block / 24;
+    int64_t cap = p.per_block / 16;
     cap = std::max<int64_t>(cap, 1024);
     cap = std::min<int64_t>(cap, kU16EpochEvents);
     return (int32_t)cap;
@@ -408,7 +408,7 @@ static int lean_layout(const hist_s *h, const Plan &p, FillArgs &a)
     const int64_t cache_b = p.lds_cache >= 0 ? cache_bytes(p.cache_slots, false) : 0;
     int64_t wl = p.win_len, total = 0;
     for (;;) {
-        total = a16(((wl + 1) / 2) * 4) + a16(model_b) + kRedBytes + 16 + cache_b;
+        total = a16(((wl + 1) / 2) * 4) + a16(model_b) + kRedBytes + 64 + cache_b;
         if (total <= h->lds_max)
             break;
         wl -= 64;
@@ -420,7 +420,7 @@ static int lean_layout(const hist_s *h, const Plan &p, FillArgs &a)
     a.lds_win = 0;
     a.ax[0].lds_model = (int32_t)win_b;
     a.lds_red = (int32_t)(win_b + a16(model_b));
-    a.lds_cache = p.lds_cache >= 0 ? a.lds_red + kRedBytes + 16 : -1;
+    a.lds_cache = p.lds_cache >= 0 ? a.lds_red + kRedBytes + 64 : -1;
     a.rare_cap = lean_rare_cap(p);
     return (int)total;
 }
