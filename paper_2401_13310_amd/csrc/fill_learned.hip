@@ -8,16 +8,17 @@
 //   - the LDS window of 16-bit counters starts at LDS offset 0, so a counter's
 //     word address is a shift of its bin;
 //   - the learned index gives a one-bin interval for most events (the bin is
-//     known without reading an edge); the others (two or more candidates) are
-//     appended to a per-workgroup list in global memory and resolved after the
-//     workgroup's last batch, with the edge reads from L2/HBM.  The event loop
-//     therefore issues no edge loads at all: loads of a wave complete in issue
-//     order, so an edge load behind the next batch's loads would wait for
-//     them.  The next batch is requested first thing in every iteration;
+//     known without reading an edge); the coordinates of the others (two or
+//     more candidates) go to a per-thread list in global memory and are
+//     resolved after the workgroup's last batch, with the edge reads from
+//     L2/HBM.  The event loop therefore issues no edge loads at all: loads of
+//     a wave complete in issue order, so an edge load behind the next batch's
+//     loads would wait for them.  The next batch is requested first thing in
+//     every iteration;
 //   - flow events and bins outside the window take the shared spill path (LDS
 //     hot-bin cache, then global atomics);
-//   - in-range events are counted by wave votes (scalar), x and x^2 summed per
-//     thread.
+//   - in-range events are counted as all events less the flow events (which
+//     take the spill path anyway), x and x^2 summed per thread.
 // When a workgroup's list is full the remaining candidates are searched in the
 // loop (correct, slower; adversarial inputs only).
 #include "fill_body.h"
@@ -71,7 +72,6 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
     extern __shared__ __align__(16) char smem[];
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    const int lane = tid & (kWave - 1);
     const AxisDev &ax = A.ax[0];
     const int64_t start = (int64_t)blockIdx.x * A.per_block;
     const int64_t end = start + A.per_block < A.n ? start + A.per_block : A.n;
@@ -82,12 +82,8 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
     // rare-list counter and the hot-bin cache (offsets from the host)
     uint32_t *win = reinterpret_cast<uint32_t *>(smem);
     const ModelSeg *model = reinterpret_cast<const ModelSeg *>(smem + ax.lds_model);
-    // the list of a workgroup is cut into one region per wave, filled with a
-    // wave-private (scalar) count: no atomics; the counts go to LDS at the end
-    uint32_t *rare_n = reinterpret_cast<uint32_t *>(smem + A.lds_red + kRedBytes);
-    const int nwaves = nthr / kWave;
-    const uint32_t wcap = (uint32_t)A.rare_cap / (uint32_t)nwaves;
-    const int wave = tid / kWave;
+    // the list of a workgroup holds tcap coordinates per thread, thread t's
+    // k-th at [k * threads + t]; a thread's count stays in a register
     {
         // the model, with the window's first bin subtracted from its offsets
         ModelSeg *dst = reinterpret_cast<ModelSeg *>(smem + ax.lds_model);
@@ -104,7 +100,8 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
     __syncthreads();
 
     const uint32_t kadd = 0x80000000u - ax.key0;
-    uint4 *rare = A.rare + (int64_t)blockIdx.x * A.rare_cap;
+    double *rare = reinterpret_cast<double *>(A.rare + (int64_t)blockIdx.x * A.rare_cap);
+    const uint32_t tcap = 2u * (uint32_t)A.rare_cap / (uint32_t)nthr;
     const uint32_t len = (uint32_t)(end > start ? end - start : 0);
     const uint32_t step = (uint32_t)nthr * U;
     __amdgpu_buffer_rsrc_t xb[1] = {column_rsrc(static_cast<const double *>(A.coords[0]) + start,
@@ -116,7 +113,7 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
 
     double sx = 0.0, sxx = 0.0;
     uint32_t nok = 0, nflow = 0;   // events of this thread, and those out of range
-    uint32_t wcount = 0;           // records this wave has listed (wave-uniform)
+    uint32_t tcount = 0;           // coordinates this thread has listed
     int it = 0;
     // full batches need no per-event range check; the block's partial last
     // batch runs the same body with one
@@ -173,27 +170,14 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
                     spill<false>(A, smem, in ? a + A.win_lo : (under ? 0 : ax.nbins + 1), 1.0);
                 }
             }
-            // several candidate bins: a slot in the workgroup's list, reserved
-            // once per wave, then one 16-byte record (x, lo, hi)
-            const bool rare_ev = ok && in && !one;
-            const uint64_t rmask = __builtin_amdgcn_ballot_w64(rare_ev);
-            if (rmask) {
-                const uint32_t first = wcount;
-                wcount += (uint32_t)__builtin_popcountll(rmask);
-                if (rare_ev) {
-                    const uint32_t idx =
-                        first + __builtin_amdgcn_mbcnt_hi((uint32_t)(rmask >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)rmask, 0u));
-                    const int32_t lo = a + A.win_lo, h = b + A.win_lo;
-                    if (idx < wcap) {
-                        const uint64_t xb64 = (uint64_t)__double_as_longlong(x[j]);
-                        rare[wave * wcap + idx] = make_uint4((uint32_t)xb64, (uint32_t)(xb64 >> 32),
-                                                             (uint32_t)lo, (uint32_t)h);
-                    } else {
-                        // the list is full: search here
-                        lean_search_add(A, smem, win, x[j], lo, h);
-                    }
-                }
+            // several candidate bins: the coordinate goes to this thread's
+            // list (the interval is evaluated again when it is resolved)
+            if (ok && in && !one) {
+                if (tcount < tcap)
+                    rare[tcount * (uint32_t)nthr + tid] = x[j];
+                else
+                    lean_search_add(A, smem, win, x[j], a + A.win_lo, b + A.win_lo);   // list full
+                ++tcount;
             }
         }
         nok += FULL ? (uint32_t)U : 0u;
@@ -217,30 +201,33 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
 
     // resolve the listed events: counters drained first, so the at most
     // rare_cap (<= kU16EpochEvents) increments cannot overflow them.  Eight
-    // records per thread at a time, their first edge reads issued together.
-    if (lane == 0)
-        rare_n[wave] = wcount < wcap ? wcount : wcap;
+    // coordinates per thread at a time, their first edge reads issued
+    // together.
     __syncthreads();
     drain_u16(win, (A.win_len + 1) >> 1, A.win_lo, A.cnt);
     __syncthreads();
     {
         constexpr int R = 8;
-        const uint32_t total = (uint32_t)nwaves * wcap;
-        for (uint32_t c = 0; c < total; c += (uint32_t)nthr * R) {
+        const uint32_t mine = tcount < tcap ? tcount : tcap;
+        for (uint32_t k0 = 0; k0 < mine; k0 += R) {
             double xv[R], ev[R];
             int32_t lo[R], hi[R];
-            bool valid[R];
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const uint32_t i = c + (uint32_t)j * nthr + tid;
-                valid[j] = i < total && wcap > 0 && i % wcap < rare_n[i / wcap];
-                uint4 r = make_uint4(0u, 0u, 1u, 0u);
-                if (valid[j])
-                    r = rare[i];
-                xv[j] = __longlong_as_double((int64_t)(((uint64_t)r.y << 32) | r.x));
-                lo[j] = (int32_t)r.z;
-                hi[j] = (int32_t)r.w;
-                if (lo[j] > hi[j]) {   // an interval the model could not bound: the whole axis
+                const bool valid = k0 + j < mine;
+                xv[j] = valid ? rare[(k0 + j) * (uint32_t)nthr + tid] : 0.0;
+                int32_t sj;
+                float zj;
+                lean_seg<FEAT>(xv[j], ax, kadd, sj, zj);
+                const ModelSeg mj = model[sj];
+                const float y = model_eval(mj, zj);
+                lo[j] = (int32_t)((uint32_t)mj.ai + (uint32_t)(int32_t)__builtin_ceilf(y)) + A.win_lo;
+                hi[j] = (int32_t)((uint32_t)mj.ai + (uint32_t)(int32_t)__builtin_floorf(y + half_hi(mj.cw))) +
+                        A.win_lo;
+                if (!valid) {
+                    lo[j] = 1;
+                    hi[j] = 1;
+                } else if (lo[j] > hi[j]) {   // no bound from the model: the whole axis
                     lo[j] = 1;
                     hi[j] = ax.nbins;
                 }
@@ -258,7 +245,7 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
             }
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                if (valid[j]) {
+                if (k0 + j < mine) {
                     search_one(xv[j], ax.edges, ax.nbins, lo[j], hi[j]);
                     lean_add(A, smem, win, lo[j]);
                 }
