@@ -3,24 +3,26 @@
 // variable-bin fill the benchmark times (arXiv:2401.13310 Sec. 3.1 find bin,
 // weight increment and statistics; Sec. 3.2 two-stage accumulation).
 //
-// The general fill body issues about 60 vector instructions per event here.
-// This kernel is the same computation laid out for the common case:
-//   - the LDS window of 16-bit counters starts at LDS offset 0, so a counter's
-//     word address is a shift of its bin;
-//   - the learned index gives a one-bin interval for most events (the bin is
-//     known without reading an edge); the coordinates of the others (two or
-//     more candidates) go to a per-thread list in global memory and are
-//     resolved after the workgroup's last batch, with the edge reads from
-//     L2/HBM.  The event loop therefore issues no edge loads at all: loads of
-//     a wave complete in issue order, so an edge load behind the next batch's
-//     loads would wait for them.  The next batch is requested first thing in
-//     every iteration;
-//   - flow events and bins outside the window take the shared spill path (LDS
-//     hot-bin cache, then global atomics);
-//   - in-range events are counted as all events less the flow events (which
-//     take the spill path anyway), x and x^2 summed per thread.
-// When a workgroup's list is full the remaining candidates are searched in the
-// loop (correct, slower; adversarial inputs only).
+// The general fill body spends about 60 vector instructions per event here.
+// This kernel is the same computation laid out for the common case, with
+// few branches:
+//   - the LDS window of 16-bit counters starts at LDS address 0, so a
+//     counter's address is twice its bin;
+//   - the learned index gives an interval of one or two bins for nearly every
+//     event (three or more only for models with wide segments, a kernel
+//     variant of its own).  A two-bin interval is decided by one edge: every
+//     lane issues one edge read per event, from the edge array in L2/HBM for
+//     a two-bin interval and of a +inf stored after the last edge otherwise,
+//     so no lane branches on it.  The edge reads of a batch are issued after
+//     the loads of the next batch (loads of a wave complete in issue order,
+//     and the next batch is needed first in any case), then the batch's
+//     counters are added once they arrive;
+//   - flow events, bins outside the window and (in the wide variant) intervals
+//     of three or more bins take the shared spill path (LDS hot-bin cache,
+//     then global atomics) or an exact search, under a branch the wave skips
+//     when none of its lanes needs it;
+//   - in-range events are counted as all events less the flow events, x and
+//     x^2 summed per thread.
 #include "fill_body.h"
 
 namespace hg {
@@ -51,6 +53,19 @@ __device__ __forceinline__ void lean_add(const FillArgs &A, char *smem, uint32_t
         spill<false>(A, smem, g, 1.0);
 }
 
+// Adds v to the 16-bit window counter at LDS byte address ta (even): the
+// 32-bit word at ta & ~3, shifted by 16 for the upper half.  The kernel has
+// no static LDS, so the window (at offset 0 of the dynamic LDS) starts at LDS
+// address 0.  The shift is the hardware's, which takes the amount modulo 32
+// ((8 ta) mod 32 is 16 for the upper half, 0 for the lower).
+__device__ __forceinline__ void window_add(uint32_t ta, uint32_t v)
+{
+    uint32_t inc;
+    asm("v_lshlrev_b32 %0, %1, %2" : "=v"(inc) : "v"(ta << 3), "v"(v));
+    __hip_atomic_fetch_add(reinterpret_cast<__attribute__((address_space(3))) uint32_t *>((size_t)(ta & ~3u)), inc,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // The bin of an in-range x known to lie in [lo, hi] (global bins; lo > hi:
 // the model gave no bound, the whole axis), found by binary search over the
 // edges, then added.
@@ -65,7 +80,15 @@ __device__ __forceinline__ void lean_search_add(const FillArgs &A, char *smem, u
     lean_add(A, smem, win, lo);
 }
 
-template <int FEAT>
+// Markers in place of twice a window bin (which stays far from them, the
+// histogram having fewer than 2^28 bins): the event is out of range, or its
+// interval holds more than two bins.  Adding 2 keeps them apart.
+constexpr uint32_t kMarkOut = 0x80000000u;
+constexpr uint32_t kMarkWide = 0x80000010u;
+
+// WIDE: the index may give intervals of three or more bins (some segment's
+// width is 2 or more); else every interval holds one or two.
+template <int FEAT, bool WIDE>
 __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArgs A)
 {
     constexpr int U = kLeanU;
@@ -78,12 +101,10 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
 
     if (start == 0 && tid == 0 && A.entries)
         gl_add_u64(A.entries, (uint64_t)A.n);
-    // LDS: the window at 0, then the model, the statistics partials, the
-    // rare-list counter and the hot-bin cache (offsets from the host)
+    // LDS: the window at 0, then the model, the statistics partials and the
+    // hot-bin cache (offsets from the host)
     uint32_t *win = reinterpret_cast<uint32_t *>(smem);
     const ModelSeg *model = reinterpret_cast<const ModelSeg *>(smem + ax.lds_model);
-    // the list of a workgroup holds tcap coordinates per thread, thread t's
-    // k-th at [k * threads + t]; a thread's count stays in a register
     {
         // the model, with the window's first bin subtracted from its offsets
         ModelSeg *dst = reinterpret_cast<ModelSeg *>(smem + ax.lds_model);
@@ -100,8 +121,10 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
     __syncthreads();
 
     const uint32_t kadd = 0x80000000u - ax.key0;
-    double *rare = reinterpret_cast<double *>(A.rare + (int64_t)blockIdx.x * A.rare_cap);
-    const uint32_t tcap = 2u * (uint32_t)A.rare_cap / (uint32_t)nthr;
+    // the edges and, after e[nbins], the +inf the lanes without a choice read
+    const __amdgpu_buffer_rsrc_t eb = column_rsrc(ax.edges, (uint32_t)(ax.nbins + 2) * (uint32_t)sizeof(double));
+    const uint32_t inf_off = (uint32_t)(ax.nbins + 1) * (uint32_t)sizeof(double);
+    const uint32_t wlo8 = (uint32_t)A.win_lo * (uint32_t)sizeof(double);
     const uint32_t len = (uint32_t)(end > start ? end - start : 0);
     const uint32_t step = (uint32_t)nthr * U;
     __amdgpu_buffer_rsrc_t xb[1] = {column_rsrc(static_cast<const double *>(A.coords[0]) + start,
@@ -113,7 +136,7 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
 
     double sx = 0.0, sxx = 0.0;
     uint32_t nok = 0, nflow = 0;   // events of this thread, and those out of range
-    uint32_t tcount = 0;           // coordinates this thread has listed
+    const uint32_t wlen2 = 2u * (uint32_t)A.win_len;
     int it = 0;
     // full batches need no per-event range check; the block's partial last
     // batch runs the same body with one
@@ -123,7 +146,8 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
 #pragma unroll
         for (int j = 0; j < U; ++j)
             x[j] = cx[j][0];
-        // the next batch first: no later load of this wave waits behind it
+        // the next batch first: loads complete in issue order, so the edge
+        // reads below wait for it in any case
         load_batch<1, double, false, U>(xb, wb, base + step, cx, cw);
         __builtin_amdgcn_sched_barrier(0);
 
@@ -138,53 +162,58 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
             m[j] = model[s[j]];
         __builtin_amdgcn_sched_barrier(0);
 
-        // each event is finished before the next one is looked at, so no
-        // per-event masks stay live across the batch.  Bins are in window
-        // coordinates (the staged model's offsets have the window start
-        // subtracted).
+        // The interval [a, b] of the index.  t[j] is twice the lower bin a in
+        // window coordinates (the staged model's offsets have the window
+        // start subtracted), the byte address of its counter, or a marker.
+        // A two-bin interval is decided by one edge, e[a] in global bins:
+        // below it the event is in a, else in a + 1; the other lanes read
+        // +inf and stay in a.
+        uint32_t t[U];
+        double e[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const bool ok = FULL || base + (uint32_t)j * nthr + tid < len;
             // for an in-range x, y stays within the segment's bins: the
-            // conversions cannot overflow (an infinite width saturates and
-            // is caught as an empty interval)
+            // conversions cannot overflow (an infinite width gives NaN or
+            // infinite differences, hence the wide marker)
             const float y = model_eval(m[j], z[j]);
-            const int32_t a = (int32_t)((uint32_t)m[j].ai + (uint32_t)(int32_t)__builtin_ceilf(y));
-            const int32_t b =
-                (int32_t)((uint32_t)m[j].ai + (uint32_t)(int32_t)__builtin_floorf(y + half_hi(m[j].cw)));
-            const bool under = x[j] < ax.xmin;
-            const bool in = !under && x[j] < ax.xmax;   // false for NaN
-            const bool inw = (uint32_t)a < (uint32_t)A.win_len;
-            const bool one = a == b;
-            if (ok && in && one && inw)
-                lds_add_u32(&win[(uint32_t)a >> 1], 1u << (((uint32_t)a & 1u) << 4));
+            const float fa = __builtin_ceilf(y);
+            const float d = __builtin_floorf(y + half_hi(m[j].cw)) - fa;   // bins in the interval - 1
+            const uint32_t tj = ((uint32_t)m[j].ai + (uint32_t)(int32_t)fa) << 1;
+            const bool in = ok && !(x[j] < ax.xmin) && x[j] < ax.xmax;   // false for NaN
+            t[j] = !in ? kMarkOut : (!WIDE || d <= 1.0f) ? tj : kMarkWide;
+            const uint32_t eo = in && (WIDE ? d == 1.0f : d != 0.0f) ? 4u * tj + wlo8 : inf_off;
+            e[j] = buffer_load_nt<double>(eb, eo);
             // statistics sums of in-range events
-            const double xm = ok && in ? x[j] : 0.0;
+            const double xm = in ? x[j] : 0.0;
             sx += xm;
             sxx = __builtin_fma(xm, xm, sxx);
-            // flow events and bins outside the window: the spill path
-            const bool sp = ok && (!in || (one && !inw));
-            if (__builtin_amdgcn_ballot_w64(sp)) {
-                if (sp) {
-                    nflow += in ? 0u : 1u;
-                    spill<false>(A, smem, in ? a + A.win_lo : (under ? 0 : ax.nbins + 1), 1.0);
-                }
-            }
-            // several candidate bins: the coordinate goes to this thread's
-            // list (the interval is evaluated again when it is resolved)
-            if (ok && in && !one) {
-                if (tcount < tcap)
-                    rare[tcount * (uint32_t)nthr + tid] = x[j];
-                else
-                    lean_search_add(A, smem, win, x[j], a + A.win_lo, b + A.win_lo);   // list full
-                ++tcount;
-            }
         }
         nok += FULL ? (uint32_t)U : 0u;
         if (!FULL) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
                 nok += base + (uint32_t)j * nthr + tid < len ? 1u : 0u;
+        }
+
+        // Each event's bin: in the window, its 16-bit counter; else the spill
+        // path, which also takes flow events and searches the wide intervals.
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t b2 = t[j] + (x[j] < e[j] ? 0u : 2u);
+            const bool fast = b2 < wlen2;
+            if (fast)
+                window_add(b2, 1u);
+            else if (FULL || base + (uint32_t)j * nthr + tid < len) {
+                if ((b2 & ~31u) != kMarkOut) {        // in range, outside the window
+                    spill<false>(A, smem, ((int32_t)b2 >> 1) + A.win_lo, 1.0);
+                } else if (WIDE && b2 >= kMarkWide) {   // three or more candidate bins
+                    lean_search_add(A, smem, win, x[j], 1, 0);
+                } else {                                // flow
+                    ++nflow;
+                    spill<false>(A, smem, x[j] < ax.xmin ? 0 : ax.nbins + 1, 1.0);
+                }
+            }
         }
         if (++it == A.epoch_iters) {
             it = 0;
@@ -199,60 +228,6 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
     for (; base < len; base += step)
         iteration(base, std::false_type{});
 
-    // resolve the listed events: counters drained first, so the at most
-    // rare_cap (<= kU16EpochEvents) increments cannot overflow them.  Eight
-    // coordinates per thread at a time, their first edge reads issued
-    // together.
-    __syncthreads();
-    drain_u16(win, (A.win_len + 1) >> 1, A.win_lo, A.cnt);
-    __syncthreads();
-    {
-        constexpr int R = 8;
-        const uint32_t mine = tcount < tcap ? tcount : tcap;
-        for (uint32_t k0 = 0; k0 < mine; k0 += R) {
-            double xv[R], ev[R];
-            int32_t lo[R], hi[R];
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                const bool valid = k0 + j < mine;
-                xv[j] = valid ? rare[(k0 + j) * (uint32_t)nthr + tid] : 0.0;
-                int32_t sj;
-                float zj;
-                lean_seg<FEAT>(xv[j], ax, kadd, sj, zj);
-                const ModelSeg mj = model[sj];
-                const float y = model_eval(mj, zj);
-                lo[j] = (int32_t)((uint32_t)mj.ai + (uint32_t)(int32_t)__builtin_ceilf(y)) + A.win_lo;
-                hi[j] = (int32_t)((uint32_t)mj.ai + (uint32_t)(int32_t)__builtin_floorf(y + half_hi(mj.cw))) +
-                        A.win_lo;
-                if (!valid) {
-                    lo[j] = 1;
-                    hi[j] = 1;
-                } else if (lo[j] > hi[j]) {   // no bound from the model: the whole axis
-                    lo[j] = 1;
-                    hi[j] = ax.nbins;
-                }
-            }
-            first_step_loads<R>(ax.edges, ax.nbins, lo, hi, ev);
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                if (lo[j] < hi[j]) {
-                    const int32_t mid = (lo[j] + hi[j] + 1) >> 1;
-                    if (!(xv[j] < ev[j]))
-                        lo[j] = mid;
-                    else
-                        hi[j] = mid - 1;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < R; ++j) {
-                if (k0 + j < mine) {
-                    search_one(xv[j], ax.edges, ax.nbins, lo[j], hi[j]);
-                    lean_add(A, smem, win, lo[j]);
-                }
-            }
-        }
-    }
-
     const double nin = (double)(nok - nflow);
     double st[4] = {nin, nin, sx, sxx};
     __syncthreads();
@@ -264,23 +239,23 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
 bool learned_lean_supported(int dims, bool f32, bool weighted, int acc, const AxisDev *ax)
 {
     return dims == 1 && !f32 && !weighted && acc == ACC_U16 && ax[0].kind == AX_LEARNED &&
-           ax[0].lds_edges < 0;
+           ax[0].lds_edges < 0 && ax[0].nbins < (1 << 28);
 }
 
-hipError_t launch_fill_learned(int threads, int blocks, size_t lds, const FillArgs &a, hipStream_t s)
+hipError_t launch_fill_learned(int threads, int blocks, size_t lds, bool wide, const FillArgs &a, hipStream_t s)
 {
     const AxisDev &ax = a.ax[0];
     const int feat = ax.feature == FEAT_LINEAR ? 2 : (ax.keypos ? 0 : 1);
-    const void *k = feat == 0 ? reinterpret_cast<const void *>(fill_learned_kernel<0>)
-                  : feat == 1 ? reinterpret_cast<const void *>(fill_learned_kernel<1>)
-                              : reinterpret_cast<const void *>(fill_learned_kernel<2>);
-    allow_big_lds_ptr(k);
-    if (feat == 0)
-        hipLaunchKernelGGL(fill_learned_kernel<0>, dim3(blocks), dim3(threads), lds, s, a);
-    else if (feat == 1)
-        hipLaunchKernelGGL(fill_learned_kernel<1>, dim3(blocks), dim3(threads), lds, s, a);
+    auto go = [&](auto kernel) {
+        allow_big_lds_ptr(reinterpret_cast<const void *>(kernel));
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(threads), lds, s, a);
+    };
+    if (wide)
+        feat == 0 ? go(fill_learned_kernel<0, true>) : feat == 1 ? go(fill_learned_kernel<1, true>)
+                                                                 : go(fill_learned_kernel<2, true>);
     else
-        hipLaunchKernelGGL(fill_learned_kernel<2>, dim3(blocks), dim3(threads), lds, s, a);
+        feat == 0 ? go(fill_learned_kernel<0, false>) : feat == 1 ? go(fill_learned_kernel<1, false>)
+                                                                  : go(fill_learned_kernel<2, false>);
     return hipGetLastError();
 }
 

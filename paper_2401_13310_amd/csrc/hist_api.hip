@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -205,10 +206,15 @@ extern "C" hist_status hist_create(int dims, const hist_axis *axes, uint32_t fla
             d.kind = AX_BSEARCH;
             d.xmin = ax.edges[0];
             d.xmax = ax.edges[ax.nbins];
-            hipError_t e = dalloc(&h->d_edges[a], (size_t)ax.nbins + 1);
+            // the edges, then +inf (a learned fill's lanes that need no edge
+            // read it)
+            const double inf = std::numeric_limits<double>::infinity();
+            hipError_t e = dalloc(&h->d_edges[a], (size_t)ax.nbins + 2);
             if (e == hipSuccess)
                 e = hipMemcpy(h->d_edges[a], ax.edges, sizeof(double) * (ax.nbins + 1),
                               hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(h->d_edges[a] + ax.nbins + 1, &inf, sizeof(double), hipMemcpyHostToDevice);
             if (e != hipSuccess) {
                 free_handle(h);
                 return set_error(e == hipErrorOutOfMemory ? HIST_ENOMEM : HIST_EDEVICE,
@@ -382,25 +388,9 @@ static bool use_learned_lean(const hist_s *h, const Plan &p, bool f32, bool weig
            learned_lean_supported(h->dims, f32, weighted, p.acc, h->ax);
 }
 
-// Records of its per-workgroup list of events with several candidate bins
-// (one region per wave): about one in 16 events of a workgroup (the learned
-// index leaves a few per cent), at most one 16-bit counter epoch.
-static int32_t lean_rare_cap(const Plan &p)
-{
-    int64_t cap = p.per_block / 16;
-    cap = std::max<int64_t>(cap, 1024);
-    cap = std::min<int64_t>(cap, kU16EpochEvents);
-    return (int32_t)cap;
-}
-
-static size_t lean_rare_bytes(const Plan &p)
-{
-    return (size_t)p.blocks * (size_t)lean_rare_cap(p) * sizeof(uint4);
-}
-
-// Its LDS layout: the window at 0, the model, the statistics partials and the
-// list count, the hot-bin cache; the window gives up bins (a few, from its top)
-// if the LDS would be exceeded.  Returns the LDS bytes, 0 if no window fits.
+// Its LDS layout: the window at 0, the model, the statistics partials, the
+// hot-bin cache; the window gives up bins (a few, from its top) if the LDS
+// would be exceeded.  Returns the LDS bytes, 0 if no window fits.
 static int lean_layout(const hist_s *h, const Plan &p, FillArgs &a)
 {
     auto a16 = [](int64_t x) { return (x + 15) & ~(int64_t)15; };
@@ -408,7 +398,7 @@ static int lean_layout(const hist_s *h, const Plan &p, FillArgs &a)
     const int64_t cache_b = p.lds_cache >= 0 ? cache_bytes(p.cache_slots, false) : 0;
     int64_t wl = p.win_len, total = 0;
     for (;;) {
-        total = a16(((wl + 1) / 2) * 4) + a16(model_b) + kRedBytes + 64 + cache_b;
+        total = a16(((wl + 1) / 2) * 4) + a16(model_b) + kRedBytes + cache_b;
         if (total <= h->lds_max)
             break;
         wl -= 64;
@@ -420,8 +410,7 @@ static int lean_layout(const hist_s *h, const Plan &p, FillArgs &a)
     a.lds_win = 0;
     a.ax[0].lds_model = (int32_t)win_b;
     a.lds_red = (int32_t)(win_b + a16(model_b));
-    a.lds_cache = p.lds_cache >= 0 ? a.lds_red + kRedBytes + 64 : -1;
-    a.rare_cap = lean_rare_cap(p);
+    a.lds_cache = p.lds_cache >= 0 ? a.lds_red + kRedBytes : -1;
     return (int)total;
 }
 
@@ -722,10 +711,8 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
     const int lean_lds = lean ? lean_layout(h, p, a) : 0;
     if (lean && lean_lds <= 0)
         return set_error(HIST_EINVAL, "hist_fill: no LDS layout for the learned kernel");
-    if (p.merge == MERGE_STAGE || lean) {
-        // staging slots (staged merge), then the learned kernel's lists
-        const size_t stage_b = p.merge == MERGE_STAGE ? stage_bytes_for(p) : 0;
-        const size_t want = up256(stage_b) + (lean ? lean_rare_bytes(p) : 0);
+    if (p.merge == MERGE_STAGE) {
+        const size_t stage_b = stage_bytes_for(p);
         char *base = nullptr;
         if (fx) {
             if (stage_b > fx->bytes)
@@ -733,22 +720,14 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
                                               "bytes) exceed the %zu-byte scratch",
                                  stage_b, fx->bytes);
             base = fx->base;
-            if (lean) {
-                // the lists take what the region has left (a full list is
-                // searched in place)
-                const size_t room = (fx->bytes - up256(stage_b)) / ((size_t)p.blocks * sizeof(uint4));
-                a.rare_cap = (int32_t)std::min<size_t>((size_t)a.rare_cap, room);
-            }
         } else {
-            hist_status st = ensure_stage(h, want, s);
+            hist_status st = ensure_stage(h, stage_b, s);
             if (st != HIST_OK)
                 return st;
             base = static_cast<char *>(h->d_stage);
         }
         a.stage = base;
         a.stage_stride = p.acc == ACC_U16 ? (a.win_len + 1) / 2 : a.win_len;
-        if (lean)
-            a.rare = reinterpret_cast<uint4 *>(base + up256(stage_b));
     }
     const int t0 = h->timing ? timing_event(h) : -1;
     if (t0 >= 0)
@@ -760,7 +739,8 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
         if (p.stats_ept > 0)
             HIPCHK(launch_stats_separate(weighted, p.stats_ept, h->num_cu, a, s), "statistics launch");
     } else if (lean) {
-        HIPCHK(launch_fill_learned(p.threads, p.blocks, (size_t)lean_lds, a, s), "fill launch");
+        HIPCHK(launch_fill_learned(p.threads, p.blocks, (size_t)lean_lds, !h->index_narrow[0], a, s),
+               "fill launch");
     } else {
         HIPCHK(launch_fill(h->dims, f32, p.acc, weighted, p.threads, p.blocks, (size_t)p.lds, a, s),
                "fill launch");
@@ -879,11 +859,8 @@ hist_status hg::reserve_scratch(hist_s *h, int64_t n_max, hist_dtype dtype, bool
     // plan of n_max events bounds every smaller fill.
     const Plan p = make_plan(h, n_max, dtype, weighted);
     hist_status st = HIST_OK;
-    const bool lean = use_learned_lean(h, p, dtype == HIST_F32, weighted);
-    if (p.strategy == HIST_STRAT_LDS && (p.merge == MERGE_STAGE || lean))
-        st = ensure_stage(h, (p.merge == MERGE_STAGE ? up256(stage_bytes_for(p)) : 0) +
-                                 (lean ? lean_rare_bytes(p) : 0),
-                          s, true);
+    if (p.strategy == HIST_STRAT_LDS && p.merge == MERGE_STAGE)
+        st = ensure_stage(h, stage_bytes_for(p), s, true);
     if (st == HIST_OK && p.strategy == HIST_STRAT_TILED)
         st = ensure_gbins(h, std::min<int64_t>(n_max, tiled_chunk(h)), s, true);
     if (st == HIST_OK && p.strategy == HIST_STRAT_PART) {
@@ -1056,6 +1033,7 @@ extern "C" hist_status hist_train_index(hist_t *h, int axis, void *stream)
         e = dalloc(&d_diag, (size_t)nseg * 2);
     AxisDev cand[2];
     double score[2] = {INFINITY, INFINITY}, maxw[2] = {0, 0}, meanw[2] = {0, 0};
+    bool narrow[2] = {false, false};
     std::vector<double> diag((size_t)nseg * 2);
     for (int f = 0; f < 2 && e == hipSuccess; ++f) {
         AxisDev ax = f == 0 ? keyax : h->ax[axis];
@@ -1082,14 +1060,19 @@ extern "C" hist_status hist_train_index(hist_t *h, int axis, void *stream)
         if (e != hipSuccess)
             break;
         // edge-weighted mean candidate-interval width
-        double num = 0, den = 0, mx = 0, sm = 0;
+        double num = 0, den = 0, mx = 0, sm = 0, mxe = 0;
         for (int i = 0; i < ax.nseg; ++i) {
             const double wdt = diag[2 * i], cnt = diag[2 * i + 1] + 1.0;
             num += wdt * cnt;
             den += cnt;
             sm += wdt;
             mx = wdt > mx ? wdt : mx;
+            mxe = cnt > mxe ? cnt : mxe;
         }
+        // at most two candidate bins for every x: widths below 2 with room
+        // for the rounding of y + w (y stays within about the segment's bins,
+        // below 2^16, where an FP32 ulp is at most 2^-8)
+        narrow[f] = mx < 1.99 && mxe < 65536.0;
         score[f] = den > 0 ? num / den : INFINITY;
         maxw[f] = mx;
         meanw[f] = sm / ax.nseg;
@@ -1114,6 +1097,7 @@ extern "C" hist_status hist_train_index(hist_t *h, int axis, void *stream)
     h->index_feature[axis] = best;
     h->index_mean_window[axis] = score[best];
     h->index_max_window[axis] = maxw[best];
+    h->index_narrow[axis] = narrow[best];
     (void)meanw;
     return HIST_OK;
 }

@@ -114,10 +114,7 @@ struct FillArgs {
     uint32_t *part_totals;    // PCOUNT: events per bucket (added to with atomics)
     int32_t part_shift;       // PCOUNT: log2 of the bucket width
     int32_t total_bins;       // T (global bins of the histogram)
-    uint4 *rare;              // learned one-axis kernel: per-workgroup lists of events with
-                              // several candidate bins (rare_cap records each)
-    int32_t rare_cap;
-    int32_t lds_red;          // learned one-axis kernel: statistics partials, then the list count
+    int32_t lds_red;          // learned one-axis kernel: statistics partials
 };
 
 struct TileArgs {
@@ -191,7 +188,8 @@ hipError_t launch_stats_separate(bool weighted, int ept, int num_cu, const FillA
 // window, edges in HBM.  Its LDS: the window at 0, the model, the statistics
 // partials and list count, the hot-bin cache.
 bool learned_lean_supported(int dims, bool f32, bool weighted, int acc, const AxisDev *ax);
-hipError_t launch_fill_learned(int threads, int blocks, size_t lds, const FillArgs &a, hipStream_t s);
+// wide: the index may give intervals of three or more bins
+hipError_t launch_fill_learned(int threads, int blocks, size_t lds, bool wide, const FillArgs &a, hipStream_t s);
 hipError_t launch_findbin(int dims, bool f32, int threads, int blocks, size_t lds,
                           const FillArgs &a, int32_t *out, hipStream_t s);
 hipError_t launch_tiled_bins(int dims, bool f32, bool weighted, int threads, int blocks,

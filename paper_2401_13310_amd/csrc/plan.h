@@ -74,6 +74,7 @@ struct hist_s {
     int index_feature[hg::kMaxDims] = {0, 0, 0};
     double index_mean_window[hg::kMaxDims] = {0, 0, 0};
     double index_max_window[hg::kMaxDims] = {0, 0, 0};
+    bool index_narrow[hg::kMaxDims] = {false, false, false};   // at most two candidate bins
     uint64_t *d_cnt = nullptr;
     double *d_sumw = nullptr, *d_sumw2 = nullptr, *d_stats = nullptr;
     void *d_stage = nullptr;

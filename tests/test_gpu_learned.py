@@ -1,10 +1,11 @@
 """GPU parity of the learned one-axis kernel (one binary64 axis with a trained
 index and more edges than LDS holds, unit weights, 16-bit window): the
 benchmark workload, inputs that put nearly every event on or next to an edge
-(so most events have two candidate bins and the per-workgroup lists fill up
-and overflow into in-loop searches), a window narrower than the histogram,
-axes whose range crosses zero (key feature of signed values) and evenly
-spaced edges (linear feature)."""
+(so most intervals hold two bins and are decided by an edge read), a window
+narrower than the histogram, axes whose range crosses zero (key feature of
+signed values), evenly spaced edges (linear feature), and edges so unevenly
+spread that some segment's interval holds three or more bins (the variant that
+searches those)."""
 import numpy as np
 import pytest
 
@@ -52,7 +53,7 @@ def test_learned_benchmark_workload(hg):
     assert plan["accumulator"] == "u16" and plan["strategy"] == "lds"
 
 
-def test_learned_events_on_edges_overflow_lists(hg):
+def test_learned_events_on_edges(hg):
     e = synth.log_edges()
     rng = np.random.default_rng(51)
     up = np.nextafter(e, np.inf)
@@ -81,3 +82,20 @@ def test_learned_evenly_spaced_edges(hg):
     e = np.linspace(-5.0, 5.0, 90001)
     x = np.concatenate([rng.normal(0.0, 1.5, 2_000_000), e[::3]])
     _fill(hg, [{"nbins": len(e) - 1, "edges": e}], x)
+
+
+def test_learned_wide_intervals(hg):
+    rng = np.random.default_rng(54)
+    # a dense cluster of edges inside an otherwise sparse axis: the segment
+    # holding the cluster cannot be fitted to within two bins
+    e = np.unique(np.concatenate([np.linspace(1.0, 1000.0, 60000),
+                                  rng.uniform(7.0, 7.0 + 1e-6, 40000)]))
+    axes = [{"nbins": len(e) - 1, "edges": e}]
+    h = hg.Hist(axes)
+    h.train_index(0)
+    assert h.index_info(0)["max_window"] >= 2.0
+    x = np.concatenate([rng.uniform(0.5, 1100.0, 1_500_000), rng.uniform(7.0, 7.0 + 1e-6, 500_000),
+                        e[::5]])
+    rng.shuffle(x)
+    plan = _fill(hg, axes, x)
+    assert plan["accumulator"] == "u16" and plan["strategy"] == "lds"
