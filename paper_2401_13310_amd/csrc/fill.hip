@@ -45,8 +45,9 @@ __global__ void __launch_bounds__(kMaxThreads, kCountWavesPerSimd) fill_kernel_x
     fill_range<D, T, ACC, W, U, KS>(A, smem, start, end, blockIdx.x, gridDim.x);
 }
 
-// Sums the staging slots of `nblocks` fill workgroups into the histogram.
-// blockIdx.y selects a group of slots; groups add with coalesced atomics.
+// Sums the staging slots (32-bit counters or binary64 sums) of `nblocks` fill
+// workgroups into the histogram.  blockIdx.y selects a group of slots; groups
+// add with coalesced atomics.
 template <int ACC>
 __global__ void __launch_bounds__(256) stage_reduce_kernel(const FillArgs A, int nblocks,
                                                            int per_group)
@@ -65,23 +66,6 @@ __global__ void __launch_bounds__(256) stage_reduce_kernel(const FillArgs A, int
             s += st[(int64_t)b * A.stage_stride + u];
         if (s)
             gl_add_u64(&A.cnt[A.win_lo + u], s);
-    } else if (ACC == ACC_U16) {
-        const int words = (W + 1) >> 1;
-        if (u >= words)
-            return;
-        const uint32_t *st = static_cast<const uint32_t *>(A.stage);
-        uint64_t lo = 0, hi = 0;
-#pragma unroll 8
-        for (int b = b0; b < b1; ++b) {
-            const uint32_t v = st[(int64_t)b * A.stage_stride + u];
-            lo += v & 0xFFFFu;
-            hi += v >> 16;
-        }
-        const int64_t g0 = (int64_t)A.win_lo + 2 * u;
-        if (lo)
-            gl_add_u64(&A.cnt[g0], lo);
-        if (hi)
-            gl_add_u64(&A.cnt[g0 + 1], hi);
     } else {
         if (u >= W)
             return;
@@ -96,6 +80,48 @@ __global__ void __launch_bounds__(256) stage_reduce_kernel(const FillArgs A, int
             gl_add_f64(&A.sumw[A.win_lo + u], s);
             gl_add_f64(&A.sumw2[A.win_lo + u], s2);
         }
+    }
+}
+
+// The 16-bit slots: one workgroup per 64 consecutive words (128 bins), its 256
+// threads 16 quads of words x 16 groups of slots, 16-byte loads (slot strides
+// are multiples of four words), every thread summing up to 16 slots.  The
+// partial sums of each bin meet in LDS; one thread per bin adds the total.
+__global__ void __launch_bounds__(256) stage_reduce_u16_kernel(const FillArgs A, int nblocks)
+{
+    __shared__ uint32_t part[16][128];
+    const int q = threadIdx.x & 15;   // quad of words in the tile
+    const int g = threadIdx.x >> 4;   // group of slots: g, g + 16, ...
+    const int words = (A.win_len + 1) >> 1;
+    const int64_t w0 = (int64_t)blockIdx.x * 64 + 4 * q;
+    uint32_t sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (w0 < words) {
+        const uint32_t *st = static_cast<const uint32_t *>(A.stage) + w0;
+#pragma unroll 4
+        for (int b = g; b < nblocks; b += 16) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(st + (int64_t)b * A.stage_stride);
+            sum[0] += v.x & 0xFFFFu;
+            sum[1] += v.x >> 16;
+            sum[2] += v.y & 0xFFFFu;
+            sum[3] += v.y >> 16;
+            sum[4] += v.z & 0xFFFFu;
+            sum[5] += v.z >> 16;
+            sum[6] += v.w & 0xFFFFu;
+            sum[7] += v.w >> 16;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        part[g][8 * q + k] = sum[k];
+    __syncthreads();
+    if (threadIdx.x < 128) {
+        const int l = blockIdx.x * 128 + threadIdx.x;   // bin in the window
+        uint64_t t = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            t += part[i][threadIdx.x];
+        if (l < A.win_len && t)
+            gl_add_u64(&A.cnt[A.win_lo + l], t);
     }
 }
 
@@ -353,13 +379,17 @@ hipError_t launch_fill(int dims, bool f32, int acc, bool weighted, int threads, 
 
 hipError_t launch_stage_reduce(int acc, int blocks_used, const FillArgs &a, hipStream_t s)
 {
-    const int units = acc == ACC_U16 ? (a.win_len + 1) / 2 : a.win_len;
+    if (acc == ACC_U16) {
+        const int words = (a.win_len + 1) / 2;
+        hipLaunchKernelGGL(stage_reduce_u16_kernel, dim3((words + 63) / 64), dim3(256), 0, s, a, blocks_used);
+        return hipGetLastError();
+    }
+    const int units = a.win_len;
     const int per_group = 32;
     const int groups = (blocks_used + per_group - 1) / per_group;
     dim3 grid((units + 255) / 256, groups);
     switch (acc) {
     case ACC_U32: hipLaunchKernelGGL(stage_reduce_kernel<ACC_U32>, grid, dim3(256), 0, s, a, blocks_used, per_group); break;
-    case ACC_U16: hipLaunchKernelGGL(stage_reduce_kernel<ACC_U16>, grid, dim3(256), 0, s, a, blocks_used, per_group); break;
     default: hipLaunchKernelGGL(stage_reduce_kernel<ACC_F64>, grid, dim3(256), 0, s, a, blocks_used, per_group); break;
     }
     return hipGetLastError();

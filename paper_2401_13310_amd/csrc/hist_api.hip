@@ -727,7 +727,7 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
             base = static_cast<char *>(h->d_stage);
         }
         a.stage = base;
-        a.stage_stride = p.acc == ACC_U16 ? (a.win_len + 1) / 2 : a.win_len;
+        a.stage_stride = stage_stride_of(p.acc, a.win_len);
     }
     const int t0 = h->timing ? timing_event(h) : -1;
     if (t0 >= 0)

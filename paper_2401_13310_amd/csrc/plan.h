@@ -132,6 +132,7 @@ hist_status run_plan(hist_s *h, const Plan &p, const void *const *coords, const 
                      int64_t n, hist_dtype dtype, hipStream_t s, const FixedScratch *fx = nullptr);
 size_t stage_bytes_for(const Plan &p);
 int64_t stage_stride_for(const Plan &p);
+int64_t stage_stride_of(int acc, int64_t win_len);   // units of one staging slot
 int64_t tiled_chunk(const hist_s *h);
 int64_t part_chunk(const hist_s *h);
 // Smallest and largest log2 bucket width a PART plan can use (lo > hi: none).

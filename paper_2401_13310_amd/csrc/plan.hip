@@ -59,9 +59,14 @@ size_t stage_bytes_for(const Plan &p)
 
 int64_t stage_stride_for(const Plan &p)
 {
-    if (p.acc == ACC_U16)
-        return (p.win_len + 1) / 2;
-    return p.win_len;
+    return stage_stride_of(p.acc, p.win_len);
+}
+
+int64_t stage_stride_of(int acc, int64_t win_len)
+{
+    if (acc == ACC_U16)   // whole 16-byte quads of words
+        return ((win_len + 1) / 2 + 3) / 4 * 4;
+    return win_len;
 }
 
 int64_t tiled_chunk(const hist_s *h)
