@@ -97,17 +97,27 @@ __global__ void __launch_bounds__(256) stage_reduce_u16_kernel(const FillArgs A,
     uint32_t sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     if (w0 < words) {
         const uint32_t *st = static_cast<const uint32_t *>(A.stage) + w0;
-#pragma unroll 4
-        for (int b = g; b < nblocks; b += 16) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(st + (int64_t)b * A.stage_stride);
-            sum[0] += v.x & 0xFFFFu;
-            sum[1] += v.x >> 16;
-            sum[2] += v.y & 0xFFFFu;
-            sum[3] += v.y >> 16;
-            sum[4] += v.z & 0xFFFFu;
-            sum[5] += v.z >> 16;
-            sum[6] += v.w & 0xFFFFu;
-            sum[7] += v.w >> 16;
+        // eight slots at a time, all loads issued before any is used (slots
+        // past the last read the last one, and count 0)
+        for (int b0 = g; b0 < nblocks; b0 += 8 * 16) {
+            uint4 v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int b = b0 + 16 * k < nblocks ? b0 + 16 * k : nblocks - 1;
+                v[k] = *reinterpret_cast<const uint4 *>(st + (int64_t)b * A.stage_stride);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const uint32_t m = b0 + 16 * k < nblocks ? 0xFFFFu : 0u;
+                sum[0] += v[k].x & m;
+                sum[1] += (v[k].x >> 16) & m;
+                sum[2] += v[k].y & m;
+                sum[3] += (v[k].y >> 16) & m;
+                sum[4] += v[k].z & m;
+                sum[5] += (v[k].z >> 16) & m;
+                sum[6] += v[k].w & m;
+                sum[7] += (v[k].w >> 16) & m;
+            }
         }
     }
 #pragma unroll
