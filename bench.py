@@ -63,7 +63,8 @@ def parse():
     ap.add_argument("--ingest", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "PLAN_JSON"),
                     help="read two rocprofv3 --pmc databases of a --profile run (FETCH_SIZE, "
                          "then WRITE_SIZE), scale each by the copy kernel of known size, and "
-                         "record the fill kernel's HBM bytes per launch in --traffic")
+                         "record the HBM bytes per launch of the fill kernel and its merge kernel "
+                         "in --traffic")
     ap.add_argument("--strategy", default="tuned", choices=["tuned", "lds", "global", "tiled", "part"],
                     help="profile runs: fix the accumulation strategy instead of tuning")
     ap.add_argument("--profile", action="store_true",
@@ -73,7 +74,8 @@ def parse():
     return ap.parse_args()
 
 
-FILL_SOURCES = ("fill.hip", "fill_body.h", "hist_internal.h", "device_common.h", "kernels.h")
+FILL_SOURCES = ("fill.hip", "fill_learned.hip", "fill_shape.hip", "fill_body.h", "hist_internal.h",
+                "device_common.h", "kernels.h")
 
 
 def kernel_source_hash():
@@ -571,10 +573,12 @@ def load_traffic(path, workload, n, plan):
     return rec.get("bytes_per_launch")
 
 
-def _counter_per_dispatch(path, counter):
+def _counter_per_dispatch(path, counter, last=None):
     """{kernel name: [value per dispatch]} for one counter, from rocprofv3's
-    counter_collection.csv or its rocpd database."""
+    counter_collection.csv or its rocpd database; `last`, if given, receives
+    each kernel's last dispatch id."""
     per = {}
+    rows = []
     if path.endswith(".csv"):
         import csv
         sums = {}
@@ -584,26 +588,32 @@ def _counter_per_dispatch(path, counter):
                     continue
                 key = (int(row["Dispatch_Id"]), row["Kernel_Name"])
                 sums[key] = sums.get(key, 0.0) + float(row["Counter_Value"])
-        for (disp, kname), val in sorted(sums.items()):
-            per.setdefault(kname, []).append(val)
-        return per
-    import sqlite3
-    db = sqlite3.connect(path)
-    for disp, kname, val in db.execute(
+        rows = [(disp, kname, val) for (disp, kname), val in sorted(sums.items())]
+    else:
+        import sqlite3
+        db = sqlite3.connect(path)
+        rows = list(db.execute(
             "select dispatch_id, kernel_name, sum(value) from counters_collection "
             "where counter_name = ? group by dispatch_id, kernel_name order by dispatch_id",
-            (counter,)):
+            (counter,)))
+    for disp, kname, val in rows:
         per.setdefault(kname, []).append(val)
+        if last is not None:
+            last[kname] = max(last.get(kname, -1), int(disp))
     return per
 
 
 def ingest(args):
-    fetch = _counter_per_dispatch(args.ingest[0], "FETCH_SIZE")
+    lastd = {}
+    fetch = _counter_per_dispatch(args.ingest[0], "FETCH_SIZE", lastd)
     write = _counter_per_dispatch(args.ingest[1], "WRITE_SIZE")
     # calibration: the elementwise copy the profile run makes last (reads and
     # writes one column); the runtime's own copy kernels also move host data
     copy = [k for k in fetch if "elementwise" in k.lower() and "hg::" not in k and k in write]
-    fill = [k for k in fetch if "fill_kernel" in k]
+    # the fill kernel: the one the profile run's timed fills (after tuning)
+    # launched last
+    fill = [k for k in fetch if k in write and
+            ("fill_kernel" in k or "fill_learned_kernel" in k or "fill_shape_kernel" in k)]
     if not copy or not fill:
         raise SystemExit("ingest: need the fill kernel and the calibration copy in both runs")
     wl = build_workload(args.workload, args.events)
@@ -612,11 +622,18 @@ def ingest(args):
     ck = copy[-1]
     f_copy = sorted(fetch[ck][-3:])[len(fetch[ck][-3:]) // 2] * 1024.0
     w_copy = sorted(write[ck][-3:])[len(write[ck][-3:]) // 2] * 1024.0
-    fk = max(fill, key=lambda k: len(fetch[k]))
+    fk = max(fill, key=lambda k: lastd[k])
     last = max(1, args.steps)                 # the fills after tuning are the last ones
     fv, wv = sorted(fetch[fk][-last:]), sorted(write[fk][-last:])
     f_fill = fv[len(fv) // 2] * 1024.0
     w_fill = wv[len(wv) // 2] * 1024.0
+    # its merge kernel (staged merge), launched right after it
+    merge = [k for k in fetch if k in write and "stage_reduce" in k and lastd[k] > lastd[fk]]
+    mk = min(merge, key=lambda k: lastd[k]) if merge else None
+    f_merge = w_merge = 0.0
+    if mk:
+        mv, mw = sorted(fetch[mk][-last:]), sorted(write[mk][-last:])
+        f_merge, w_merge = mv[len(mv) // 2] * 1024.0, mw[len(mw) // 2] * 1024.0
     sf, sw = known / f_copy, known / w_copy
     with open(args.ingest[2]) as f:
         prof = json.load(f)
@@ -624,8 +641,11 @@ def ingest(args):
         raise SystemExit("ingest: the profile run used other kernel sources or sizes")
     rec = {"events": n, "kernel": fk, "source_hash": kernel_source_hash(), "plan": prof["plan"],
            "fetch_kib_raw": f_fill / 1024.0, "write_kib_raw": w_fill / 1024.0,
+           "merge_kernel": mk, "merge_fetch_kib_raw": f_merge / 1024.0,
+           "merge_write_kib_raw": w_merge / 1024.0,
            "copy_kernel": ck, "copy_bytes": known, "fetch_scale": sf, "write_scale": sw,
-           "bytes_per_launch": f_fill * sf + w_fill * sw}
+           "fill_bytes_per_launch": f_fill * sf + w_fill * sw,
+           "bytes_per_launch": (f_fill + f_merge) * sf + (w_fill + w_merge) * sw}
     try:
         with open(args.traffic) as f:
             allrec = json.load(f)
@@ -664,7 +684,11 @@ def run_single(args, wl, headline):
         torch.cuda.synchronize()
         train_ms = (time.perf_counter() - t0) * 1e3
     sample = min(n, 1 << 22)
-    h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
+    if args.strategy == "tuned":
+        h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
+    else:
+        h.set_strategy({"lds": hg.HIST_STRAT_LDS, "global": hg.HIST_STRAT_GLOBAL,
+                        "tiled": hg.HIST_STRAT_TILED, "part": hg.HIST_STRAT_PART}[args.strategy])
     plan = h.plan_info(n, hg.HIST_F32 if f32 else hg.HIST_F64, w is not None)
     if args.profile:
         for _ in range(args.steps):
@@ -696,7 +720,7 @@ def run_single(args, wl, headline):
     B, per_event = alg_bytes(wl, n)
     traffic = load_traffic(args.traffic, args.workload, n, plan)
     rl = roofline(B, kernel_ms)
-    rl.update({"traffic": traffic, "kernel": "fill_kernel + its merge kernel (one hist_fill)",
+    rl.update({"traffic": traffic, "kernel": "the fill kernel + its staged merge kernel (one hist_fill)",
                "kernel_ms": kernel_ms, "fill_kernel_ms": fill_ms, "merge_kernel_ms": merge_ms,
                "alg_bytes_per_launch": B, "alg_bytes_per_event": per_event})
     out = {
