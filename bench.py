@@ -704,7 +704,8 @@ def run_single(args, wl, headline):
               % (args.steps, n, plan, cols[0].numel() * cols[0].element_size(),
                  kernel_source_hash()), flush=True)
         os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-        with open(os.path.join(ROOT, "gpurun_out", "profile_plan_%s.json" % args.workload), "w") as f:
+        tag = args.workload if args.strategy == "tuned" else "%s_%s" % (args.workload, args.strategy)
+        with open(os.path.join(ROOT, "gpurun_out", "profile_plan_%s.json" % tag), "w") as f:
             json.dump({"workload": args.workload, "events": n, "plan": plan,
                        "source_hash": kernel_source_hash()}, f)
         h.close()
