@@ -304,9 +304,6 @@ def time_fills(h, step, steps, warmup):
     t0 = time.perf_counter()
     for _ in range(steps):
         step()
-    for x in hs:   # a merge the last fill deferred belongs to the timed work
-        if hasattr(x, "flush"):
-            x.flush()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fill = merge = 0.0
@@ -676,8 +673,6 @@ def run_single(args, wl, headline):
     cols, w = to_dev(wl)
     f32 = wl["coords"][0].dtype == np.float32
     flags = hg.HIST_F_ACC_F32C if wl["name"] == "precision" else 0
-    # repeated fills, one read: the learned fill's merge rides on the next fill
-    flags |= hg.HIST_F_DEFER_MERGE
     variable = any(a.get("edges") is not None for a in wl["axes"])
 
     h = hg.Hist(wl["axes"], flags)

@@ -85,14 +85,6 @@ typedef struct {
 #define HIST_F_NO_ALLOC   (1u << 2)  /* fills never allocate: a fill whose plan needs
                                         more scratch than hist_reserve set aside fails
                                         with HIST_ENOMEM instead of growing it       */
-#define HIST_F_DEFER_MERGE (1u << 3) /* many fills, one read (the paper's bulks, Sec.
-                                        3.3): the staged merge of a learned one-axis
-                                        fill (16-bit window) is done by the next such
-                                        fill, spread over its workgroups, instead of a
-                                        kernel of its own.  hist_read completes it;
-                                        hist_flush does so explicitly (required before
-                                        capturing a fill while a merge is pending).
-                                        Two staging buffers instead of one.          */
 
 /* Accumulation strategies (hist_set_strategy / hist_plan_info).  */
 typedef enum {
@@ -233,14 +225,8 @@ HIST_API hist_status hist_stats(hist_t *h, double *out, int cap, int *count, voi
  * fill that has run).  Synchronizes `stream`; HIST_ECAPTURE while capturing. */
 HIST_API hist_status hist_read(hist_t *h, double *sumw, double *sumw2, int64_t *entries, void *stream);
 
-/* Zero bins, statistics and entries.  Asynchronous (fill kernels, no memset).
- * A deferred merge still pending (HIST_F_DEFER_MERGE) is dropped with them. */
+/* Zero bins, statistics and entries.  Asynchronous (fill kernels, no memset). */
 HIST_API hist_status hist_reset(hist_t *h, void *stream);
-
-/* Completes the merge a HIST_F_DEFER_MERGE fill left pending, on `stream`
- * (ordered after that fill's stream); nothing to do otherwise.  Asynchronous;
- * HIST_ECAPTURE if a merge is pending and `stream` is capturing. */
-HIST_API hist_status hist_flush(hist_t *h, void *stream);
 
 /* ---- learned find-bin index --------------------------------------------- */
 

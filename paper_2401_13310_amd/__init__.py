@@ -12,8 +12,7 @@ import ctypes
 
 import numpy as np
 
-from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_DEFER_MERGE, HIST_F_LEARNED,
-                   HIST_F_NO_ALLOC,
+from ._lib import (ACC_NAMES, HIST_F32, HIST_F64, HIST_F_ACC_F32C, HIST_F_LEARNED, HIST_F_NO_ALLOC,
                    HIST_HOST_PINNED, HIST_SEARCH_BINARY, HIST_SEARCH_LEARNED, HIST_STRAT_AUTO, HIST_STRAT_GLOBAL,
                    HIST_STRAT_LDS, HIST_STRAT_PART, HIST_STRAT_TILED, STRAT_NAMES, HistAxis, HistError,
                    HistDefine, HistExpr, HistFillDesc, HistOp, check, load)
@@ -22,14 +21,13 @@ from .expr import OPS, parse
 __all__ = [
     "Hist", "HistError", "hist_create", "hist_destroy", "hist_fill", "hist_fill_static", "hist_static_scratch_bytes", "hist_fill_host", "hist_probe", "hist_findbin",
     "hist_reserve",
-    "hist_stats", "hist_read", "hist_reset", "hist_flush", "hist_train_index", "hist_set_search",
+    "hist_stats", "hist_read", "hist_reset", "hist_train_index", "hist_set_search",
     "hist_index_info", "hist_set_strategy", "hist_set_window", "hist_tune", "hist_plan_info",
     "hist_timing", "hist_timing_read", "hist_set_threads", "hist_set_shape", "hist_plan_shape",
     "hist_batch_create", "hist_batch_launch", "hist_batch_launch_eager", "hist_batch_destroy",
     "hist_multi_create", "hist_multi_fill", "hist_multi_info", "hist_multi_destroy", "Multi",
     "OPS", "parse",
-    "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_F_NO_ALLOC", "HIST_F_DEFER_MERGE",
-    "HIST_HOST_PINNED",
+    "HIST_F64", "HIST_F32", "HIST_F_ACC_F32C", "HIST_F_LEARNED", "HIST_F_NO_ALLOC", "HIST_HOST_PINNED",
     "HIST_STRAT_AUTO",
     "HIST_STRAT_LDS", "HIST_STRAT_GLOBAL", "HIST_STRAT_TILED", "HIST_STRAT_PART", "HIST_SEARCH_BINARY",
     "HIST_SEARCH_LEARNED", "Batch",
@@ -139,10 +137,6 @@ def hist_read(h, stream: int):
 
 def hist_reset(h, stream: int) -> None:
     check(load().hist_reset(h, stream), "hist_reset")
-
-
-def hist_flush(h, stream: int) -> None:
-    check(load().hist_flush(h, stream), "hist_flush")
 
 
 def hist_train_index(h, axis: int, stream: int) -> None:
@@ -388,10 +382,6 @@ class Hist:
 
     def reset(self, stream=None):
         hist_reset(self._h, _stream_ptr(stream))
-
-    def flush(self, stream=None):
-        """Completes a merge a HIST_F_DEFER_MERGE fill left pending."""
-        hist_flush(self._h, _stream_ptr(stream))
 
     def train_index(self, axis: int = 0, stream=None):
         hist_train_index(self._h, axis, _stream_ptr(stream))

@@ -19,7 +19,6 @@ HIST_F64, HIST_F32 = 0, 1
 HIST_F_ACC_F32C = 1 << 0
 HIST_F_LEARNED = 1 << 1
 HIST_F_NO_ALLOC = 1 << 2
-HIST_F_DEFER_MERGE = 1 << 3
 HIST_HOST_PINNED = 1 << 0
 (HIST_PROBE_READ, HIST_PROBE_LDS_U32, HIST_PROBE_LDS_F64, HIST_PROBE_GLOBAL_U64,
  HIST_PROBE_GLOBAL_F64) = range(5)
@@ -74,7 +73,6 @@ PROTOTYPES = {
     "hist_read": (_st, [_H, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                         ctypes.POINTER(ctypes.c_int64), _P]),
     "hist_reset": (_st, [_H, _P]),
-    "hist_flush": (_st, [_H, _P]),
     "hist_train_index": (_st, [_H, ctypes.c_int, _P]),
     "hist_set_search": (_st, [_H, ctypes.c_int, ctypes.c_int]),
     "hist_index_info": (_st, [_H, ctypes.c_int, ctypes.POINTER(ctypes.c_int),

@@ -80,62 +80,6 @@ __device__ __forceinline__ void lean_search_add(const FillArgs &A, char *smem, u
     lean_add(A, smem, win, lo);
 }
 
-// The deferred merge of the previous fill's 16-bit staging slots: this
-// workgroup's share of their words, summed over the slots and added into the
-// histogram, with the first 32 KB of the window's LDS as scratch (before the
-// window is zeroed).  1024 threads: 64 quads of words x 16 groups of slots,
-// eight slot loads per thread issued before any is used.
-__device__ __forceinline__ void merge_pending(const FillArgs &A, uint32_t *scratch)
-{
-    const int tid = threadIdx.x;
-    const int words = (A.pend_win_len + 1) >> 1;
-    const int per = (((words + (int)gridDim.x - 1) / (int)gridDim.x) + 3) & ~3;
-    const int w0 = (int)blockIdx.x * per;
-    const int q = tid & 63, g = tid >> 6;
-    const int nslot = A.pend_blocks;
-    for (int qb = 0; qb < per; qb += 256) {
-        const int wq = w0 + qb + 4 * q;
-        uint32_t sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (qb + 4 * q < per && wq < words) {
-            const uint32_t *st = static_cast<const uint32_t *>(A.pend_stage) + wq;
-            for (int b0 = g; b0 < nslot; b0 += 128) {
-                uint4 v[8];
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int b = b0 + 16 * k < nslot ? b0 + 16 * k : nslot - 1;
-                    v[k] = *reinterpret_cast<const uint4 *>(st + (int64_t)b * A.pend_stride);
-                }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const uint32_t m = b0 + 16 * k < nslot ? 0xFFFFu : 0u;
-                    sum[0] += v[k].x & m;
-                    sum[1] += (v[k].x >> 16) & m;
-                    sum[2] += v[k].y & m;
-                    sum[3] += (v[k].y >> 16) & m;
-                    sum[4] += v[k].z & m;
-                    sum[5] += (v[k].z >> 16) & m;
-                    sum[6] += v[k].w & m;
-                    sum[7] += (v[k].w >> 16) & m;
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k)
-            scratch[g * 512 + 8 * q + k] = sum[k];
-        __syncthreads();
-        if (tid < 512) {
-            const int l = 2 * (w0 + qb) + tid;   // bin in the pending window
-            uint64_t t = 0;
-#pragma unroll
-            for (int i = 0; i < 16; ++i)
-                t += scratch[i * 512 + tid];
-            if (l < A.pend_win_len && t)
-                gl_add_u64(&A.cnt[A.pend_win_lo + l], t);
-        }
-        __syncthreads();
-    }
-}
-
 // Markers in place of twice a window bin (which stays far from them, the
 // histogram having fewer than 2^28 bins): the event is out of range, or its
 // interval holds more than two bins.  Adding 2 keeps them apart.
@@ -161,8 +105,6 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
     // hot-bin cache (offsets from the host)
     uint32_t *win = reinterpret_cast<uint32_t *>(smem);
     const ModelSeg *model = reinterpret_cast<const ModelSeg *>(smem + ax.lds_model);
-    if (A.pend_blocks > 0)
-        merge_pending(A, win);
     {
         // the model, with the window's first bin subtracted from its offsets
         ModelSeg *dst = reinterpret_cast<ModelSeg *>(smem + ax.lds_model);

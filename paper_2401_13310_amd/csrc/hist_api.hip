@@ -114,13 +114,10 @@ static void free_handle(hist_s *h)
     dfree(h->d_sumw2);
     dfree(h->d_stats);
     dfree(h->d_stage);
-    dfree(h->d_stage2);
     dfree(h->d_gbins);
     dfree(h->d_part);
     for (hipEvent_t e : h->ev_pool)
         (void)hipEventDestroy(e);
-    if (h->pend_ev)
-        (void)hipEventDestroy(h->pend_ev);
     host_streamer_destroy(h->host);
     delete h;
 }
@@ -146,7 +143,7 @@ extern "C" hist_status hist_create(int dims, const hist_axis *axes, uint32_t fla
         return set_error(HIST_EINVAL, "hist_create: dims must be 1..3 (got %d)", dims);
     if (!axes)
         return set_error(HIST_EINVAL, "hist_create: axes is NULL");
-    if (flags & ~(uint32_t)(HIST_F_ACC_F32C | HIST_F_LEARNED | HIST_F_NO_ALLOC | HIST_F_DEFER_MERGE))
+    if (flags & ~(uint32_t)(HIST_F_ACC_F32C | HIST_F_LEARNED | HIST_F_NO_ALLOC))
         return set_error(HIST_EINVAL, "hist_create: unknown flags 0x%x", flags);
     int64_t T = 1;
     for (int a = 0; a < dims; ++a) {
@@ -179,11 +176,6 @@ extern "C" hist_status hist_create(int dims, const hist_axis *axes, uint32_t fla
         return set_error(HIST_ENOMEM, "hist_create: host allocation");
     h->dims = dims;
     h->flags = flags;
-    if ((flags & HIST_F_DEFER_MERGE) && hipEventCreateWithFlags(&h->pend_ev, hipEventDisableTiming) != hipSuccess) {
-        h->pend_ev = nullptr;
-        free_handle(h);
-        return set_error(HIST_EDEVICE, "hist_create: event for deferred merges");
-    }
     h->T = T;
     h->S = 2 + 2 * dims + dims * (dims - 1) / 2;
     (void)hipGetDevice(&h->device);
@@ -318,58 +310,6 @@ hist_status hg::ensure_stage(hist_s *h, size_t bytes, hipStream_t s, bool reserv
     }
     h->d_stage = p;
     h->stage_bytes = bytes;
-    return HIST_OK;
-}
-
-// The second staging buffer of deferred merges.
-static hist_status ensure_stage2(hist_s *h, size_t bytes, hipStream_t s, bool reserving)
-{
-    if (h->stage2_bytes >= bytes)
-        return HIST_OK;
-    hist_status g = may_grow(h, s, reserving, "staging buffer");
-    if (g != HIST_OK)
-        return g;
-    void *p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess)
-        return set_error(HIST_ENOMEM, "staging buffer of %zu bytes: %s", bytes, hipGetErrorString(e));
-    if (h->d_stage2) {
-        HIPCHK(hipStreamSynchronize(s), "synchronize before freeing scratch");
-        dfree(h->d_stage2);
-    }
-    h->d_stage2 = p;
-    h->stage2_bytes = bytes;
-    return HIST_OK;
-}
-
-// Completes a deferred merge on stream s: the staging slots of the last
-// deferred fill summed into the histogram by the 16-bit merge kernel.
-hist_status hg::flush_pending(hist_s *h, hipStream_t s)
-{
-    if (!h->pend)
-        return HIST_OK;
-    if (is_capturing(s))
-        return set_error(HIST_ECAPTURE, "a deferred merge is pending: call hist_flush (or hist_read) "
-                                        "before capturing");
-    if (h->pend_stream != s)
-        HIPCHK(hipStreamWaitEvent(s, h->pend_ev, 0), "deferred merge: wait for the fill");
-    FillArgs a;
-    std::memset(&a, 0, sizeof(a));
-    a.cnt = h->d_cnt;
-    a.win_lo = h->pend_win_lo;
-    a.win_len = h->pend_win_len;
-    a.stage = const_cast<void *>(h->pend_slots);
-    a.stage_stride = h->pend_stride;
-    const int t0 = h->timing ? timing_event(h) : -1;
-    if (t0 >= 0)
-        HIPCHK(hipEventRecord(h->ev_pool[t0], s), "timing event");
-    HIPCHK(launch_stage_reduce(ACC_U16, h->pend_blocks, a, s), "deferred merge launch");
-    const int t1 = h->timing ? timing_event(h) : -1;
-    if (t0 >= 0 && t1 >= 0) {
-        HIPCHK(hipEventRecord(h->ev_pool[t1], s), "timing event");
-        h->ev_merge.emplace_back(t0, t1);
-    }
-    h->pend = false;
     return HIST_OK;
 }
 
@@ -688,16 +628,6 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
     (void)hipGetLastError();
     const bool f32 = dtype == HIST_F32;
     const bool weighted = w != nullptr;
-    // a deferred merge needs the learned one-axis kernel with a staged merge
-    // and 32 KB of window LDS as scratch, outside capture
-    const bool defer = (h->flags & HIST_F_DEFER_MERGE) && !fx && p.merge == MERGE_STAGE &&
-                       p.win_len >= kDeferMinWindow && use_learned_lean(h, p, f32, weighted) &&
-                       !is_capturing(s);
-    if (!defer) {
-        hist_status st = flush_pending(h, s);
-        if (st != HIST_OK)
-            return st;
-    }
     FillArgs a = base_args(h, coords, w, n);
     apply_model_offsets(h, a);
     if (p.strategy == HIST_STRAT_PART)
@@ -791,30 +721,13 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
                                  stage_b, fx->bytes);
             base = fx->base;
         } else {
-            // buffers grow only with no merge pending on them
-            hist_status st = HIST_OK;
-            if (defer && h->pend && (h->stage_bytes < stage_b || h->stage2_bytes < stage_b))
-                st = flush_pending(h, s);
-            if (st == HIST_OK)
-                st = ensure_stage(h, stage_b, s);
-            if (st == HIST_OK && defer)
-                st = ensure_stage2(h, stage_b, s, false);
+            hist_status st = ensure_stage(h, stage_b, s);
             if (st != HIST_OK)
                 return st;
-            base = static_cast<char *>(defer && h->stage_toggle ? h->d_stage2 : h->d_stage);
+            base = static_cast<char *>(h->d_stage);
         }
         a.stage = base;
         a.stage_stride = stage_stride_of(p.acc, a.win_len);
-    }
-    if (defer && h->pend) {
-        // this fill merges the previous one's slots (the other buffer)
-        if (h->pend_stream != s)
-            HIPCHK(hipStreamWaitEvent(s, h->pend_ev, 0), "deferred merge: wait for the fill");
-        a.pend_stage = h->pend_slots;
-        a.pend_stride = h->pend_stride;
-        a.pend_blocks = h->pend_blocks;
-        a.pend_win_lo = h->pend_win_lo;
-        a.pend_win_len = h->pend_win_len;
     }
     const int t0 = h->timing ? timing_event(h) : -1;
     if (t0 >= 0)
@@ -837,18 +750,7 @@ hist_status hg::run_plan(hist_s *h, const Plan &p, const void *const *coords, co
         HIPCHK(hipEventRecord(h->ev_pool[t1], s), "timing event");
         h->ev_fill.emplace_back(t0, t1);
     }
-    if (defer) {
-        // this fill's slots wait for the next deferred fill or a flush
-        h->pend = true;
-        h->pend_slots = a.stage;
-        h->pend_stride = a.stage_stride;
-        h->pend_blocks = p.blocks;
-        h->pend_win_lo = a.win_lo;
-        h->pend_win_len = a.win_len;
-        h->pend_stream = s;
-        HIPCHK(hipEventRecord(h->pend_ev, s), "deferred merge event");
-        h->stage_toggle ^= 1;
-    } else if (p.merge == MERGE_STAGE) {
+    if (p.merge == MERGE_STAGE) {
         HIPCHK(launch_stage_reduce(p.acc, p.blocks, a, s), "stage reduce launch");
         const int t2 = h->timing ? timing_event(h) : -1;
         if (t2 >= 0) {
@@ -956,15 +858,9 @@ hist_status hg::reserve_scratch(hist_s *h, int64_t n_max, hist_dtype dtype, bool
     // workgroups up to the plan's grid, longer chunks, more buckets), so the
     // plan of n_max events bounds every smaller fill.
     const Plan p = make_plan(h, n_max, dtype, weighted);
-    // buffers may be replaced below: no deferred merge may still read them
-    hist_status st = flush_pending(h, s);
-    if (st != HIST_OK)
-        return st;
-    if (p.strategy == HIST_STRAT_LDS && p.merge == MERGE_STAGE) {
+    hist_status st = HIST_OK;
+    if (p.strategy == HIST_STRAT_LDS && p.merge == MERGE_STAGE)
         st = ensure_stage(h, stage_bytes_for(p), s, true);
-        if (st == HIST_OK && (h->flags & HIST_F_DEFER_MERGE))
-            st = ensure_stage2(h, stage_bytes_for(p), s, true);
-    }
     if (st == HIST_OK && p.strategy == HIST_STRAT_TILED)
         st = ensure_gbins(h, std::min<int64_t>(n_max, tiled_chunk(h)), s, true);
     if (st == HIST_OK && p.strategy == HIST_STRAT_PART) {
@@ -1026,9 +922,6 @@ extern "C" hist_status hist_read(hist_t *h, double *sumw, double *sumw2, int64_t
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (is_capturing(s))
         return set_error(HIST_ECAPTURE, "hist_read: stream is capturing");
-    hist_status fs = flush_pending(h, s);
-    if (fs != HIST_OK)
-        return fs;
     if (sumw || sumw2) {
         std::vector<uint64_t> cnt((size_t)h->T);
         HIPCHK(hipMemcpyAsync(cnt.data(), h->d_cnt, sizeof(uint64_t) * h->T,
@@ -1066,22 +959,7 @@ extern "C" hist_status hist_reset(hist_t *h, void *stream)
 {
     if (!h)
         return set_error(HIST_EINVAL, "hist_reset: NULL handle");
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    if (h->pend) {
-        // the pending counts are dropped; later fills reuse the slots only
-        // after the fill that wrote them
-        if (h->pend_stream != s)
-            HIPCHK(hipStreamWaitEvent(s, h->pend_ev, 0), "reset: wait for the deferred fill");
-        h->pend = false;
-    }
-    return zero_state(h, s);
-}
-
-extern "C" hist_status hist_flush(hist_t *h, void *stream)
-{
-    if (!h)
-        return set_error(HIST_EINVAL, "hist_flush: NULL handle");
-    return flush_pending(h, static_cast<hipStream_t>(stream));
+    return zero_state(h, static_cast<hipStream_t>(stream));
 }
 
 // ------------------------------------------------------- learned index ----

@@ -115,11 +115,6 @@ struct FillArgs {
     int32_t part_shift;       // PCOUNT: log2 of the bucket width
     int32_t total_bins;       // T (global bins of the histogram)
     int32_t lds_red;          // learned one-axis kernel: statistics partials
-    // learned one-axis kernel, deferred merge: the 16-bit staging slots of the
-    // previous fill (pend_blocks of them, or none) to add into cnt first
-    const void *pend_stage;
-    int64_t pend_stride;      // u32 words per slot
-    int32_t pend_blocks, pend_win_lo, pend_win_len;
 };
 
 struct TileArgs {

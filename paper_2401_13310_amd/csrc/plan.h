@@ -74,17 +74,6 @@ struct hist_s {
     int index_feature[hg::kMaxDims] = {0, 0, 0};
     double index_mean_window[hg::kMaxDims] = {0, 0, 0};
     double index_max_window[hg::kMaxDims] = {0, 0, 0};
-    // deferred merge (HIST_F_DEFER_MERGE): the staging slots of the last
-    // learned one-axis fill, merged by the next such fill or by a flush
-    void *d_stage2 = nullptr;        // second staging buffer, alternating with d_stage
-    size_t stage2_bytes = 0;
-    int stage_toggle = 0;            // the buffer the next deferred fill writes
-    bool pend = false;
-    const void *pend_slots = nullptr;
-    int64_t pend_stride = 0;
-    int32_t pend_blocks = 0, pend_win_lo = 0, pend_win_len = 0;
-    hipStream_t pend_stream = nullptr;
-    hipEvent_t pend_ev = nullptr;
     bool index_narrow[hg::kMaxDims] = {false, false, false};   // at most two candidate bins
     uint64_t *d_cnt = nullptr;
     double *d_sumw = nullptr, *d_sumw2 = nullptr, *d_stats = nullptr;
@@ -118,11 +107,6 @@ hist_status ensure_stage(hist_s *h, size_t bytes, hipStream_t s, bool reserving 
 hist_status ensure_gbins(hist_s *h, int64_t count, hipStream_t s, bool reserving = false);
 // The scratch of the plan for fills of up to n_max events (hist_reserve
 // without its synchronization).
-// Completes a deferred merge (HIST_F_DEFER_MERGE) on stream s, if one is pending.
-hist_status flush_pending(hist_s *h, hipStream_t s);
-// Windows narrower than this keep their merge kernel (the deferred merge uses
-// 32 KB of the window's LDS as scratch).
-constexpr int kDeferMinWindow = 20000;
 hist_status reserve_scratch(hist_s *h, int64_t n_max, hist_dtype dtype, bool weighted, hipStream_t s);
 FillArgs base_args(const hist_s *h, const void *const *coords, const void *w, int64_t n);
 // Places the learned models of the axes in LDS after the statistics area;

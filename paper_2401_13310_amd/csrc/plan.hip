@@ -514,10 +514,6 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
         return set_error(HIST_ECAPTURE, "hist_tune: stream is capturing");
-    // a merge deferred by an earlier fill belongs to the contents saved below
-    hist_status fs = flush_pending(h, s);
-    if (fs != HIST_OK)
-        return fs;
     const bool weighted = weights != nullptr;
     const bool f32 = dtype == HIST_F32;
 
@@ -581,7 +577,6 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
     hist_status st = save_state(h, sv, s);
     if (st != HIST_OK) {
         restore_state(h, sv, s);
-        h->pend = false;   // a trial fill's deferred merge is dropped with its counts
         return st;
     }
     hipEvent_t e0, e1;
@@ -676,7 +671,6 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     st = restore_state(h, sv, s);
-    h->pend = false;   // a trial fill's deferred merge is dropped with its counts
     h->tuned[std::make_tuple(weighted ? 1 : 0, f32 ? 1 : 0, 0)] = best;
     {
         std::lock_guard<std::mutex> lock(g_cache_mu);
