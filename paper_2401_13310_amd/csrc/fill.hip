@@ -83,19 +83,24 @@ __global__ void __launch_bounds__(256) stage_reduce_kernel(const FillArgs A, int
     }
 }
 
-// The 16-bit slots: one workgroup per 64 consecutive words (128 bins), its 256
-// threads 16 quads of words x 16 groups of slots, 16-byte loads (slot strides
-// are multiples of four words), every thread summing up to 16 slots.  The
-// partial sums of each bin meet in LDS; one thread per bin adds the total.
-__global__ void __launch_bounds__(256) stage_reduce_u16_kernel(const FillArgs A, int nblocks)
+// The 8-bit slots of the 16-bit windows: one workgroup per 64 consecutive
+// words (256 bins), its 256 threads 16 quads of words x 16 groups of slots,
+// 16-byte loads (slot strides are multiples of four words), every thread
+// summing up to 16 slots.  Eight slots at a time are summed as 16-bit halves
+// (even and odd bytes apart, at most 8 x 255 each), then widened.  The partial
+// sums of each bin meet in LDS; one thread per bin adds the total.
+__global__ void __launch_bounds__(256) stage_reduce_u8_kernel(const FillArgs A, int nblocks)
 {
-    __shared__ uint32_t part[16][128];
+    __shared__ uint32_t part[16][256];
     const int q = threadIdx.x & 15;   // quad of words in the tile
     const int g = threadIdx.x >> 4;   // group of slots: g, g + 16, ...
-    const int words = (A.win_len + 1) >> 1;
+    const int swords = (A.win_len + 3) >> 2;
     const int64_t w0 = (int64_t)blockIdx.x * 64 + 4 * q;
-    uint32_t sum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (w0 < words) {
+    uint32_t sum[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        sum[k] = 0u;
+    if (w0 < swords) {
         const uint32_t *st = static_cast<const uint32_t *>(A.stage) + w0;
         // eight slots at a time, all loads issued before any is used (slots
         // past the last read the last one, and count 0)
@@ -106,33 +111,37 @@ __global__ void __launch_bounds__(256) stage_reduce_u16_kernel(const FillArgs A,
                 const int b = b0 + 16 * k < nblocks ? b0 + 16 * k : nblocks - 1;
                 v[k] = *reinterpret_cast<const uint4 *>(st + (int64_t)b * A.stage_stride);
             }
+            uint32_t ev[4] = {0u, 0u, 0u, 0u}, od[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const uint32_t m = b0 + 16 * k < nblocks ? 0xFFFFu : 0u;
-                sum[0] += v[k].x & m;
-                sum[1] += (v[k].x >> 16) & m;
-                sum[2] += v[k].y & m;
-                sum[3] += (v[k].y >> 16) & m;
-                sum[4] += v[k].z & m;
-                sum[5] += (v[k].z >> 16) & m;
-                sum[6] += v[k].w & m;
-                sum[7] += (v[k].w >> 16) & m;
+                const uint32_t m = b0 + 16 * k < nblocks ? 0x00FF00FFu : 0u;
+                const uint32_t u[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ev[e] += u[e] & m;
+                    od[e] += (u[e] >> 8) & m;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                sum[4 * e + 0] += ev[e] & 0xFFFFu;
+                sum[4 * e + 1] += od[e] & 0xFFFFu;
+                sum[4 * e + 2] += ev[e] >> 16;
+                sum[4 * e + 3] += od[e] >> 16;
             }
         }
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        part[g][8 * q + k] = sum[k];
+    for (int k = 0; k < 16; ++k)
+        part[g][16 * q + k] = sum[k];
     __syncthreads();
-    if (threadIdx.x < 128) {
-        const int l = blockIdx.x * 128 + threadIdx.x;   // bin in the window
-        uint64_t t = 0;
+    const int l = blockIdx.x * 256 + threadIdx.x;   // bin in the window
+    uint64_t t = 0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            t += part[i][threadIdx.x];
-        if (l < A.win_len && t)
-            gl_add_u64(&A.cnt[A.win_lo + l], t);
-    }
+    for (int i = 0; i < 16; ++i)
+        t += part[i][threadIdx.x];
+    if (l < A.win_len && t)
+        gl_add_u64(&A.cnt[A.win_lo + l], t);
 }
 
 // Find bin only: the global bin of every event (grid-stride).
@@ -390,8 +399,8 @@ hipError_t launch_fill(int dims, bool f32, int acc, bool weighted, int threads, 
 hipError_t launch_stage_reduce(int acc, int blocks_used, const FillArgs &a, hipStream_t s)
 {
     if (acc == ACC_U16) {
-        const int words = (a.win_len + 1) / 2;
-        hipLaunchKernelGGL(stage_reduce_u16_kernel, dim3((words + 63) / 64), dim3(256), 0, s, a, blocks_used);
+        const int swords = (a.win_len + 3) / 4;
+        hipLaunchKernelGGL(stage_reduce_u8_kernel, dim3((swords + 63) / 64), dim3(256), 0, s, a, blocks_used);
         return hipGetLastError();
     }
     const int units = a.win_len;

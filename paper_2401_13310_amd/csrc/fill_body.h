@@ -75,9 +75,25 @@ __device__ __forceinline__ void merge_window(uint32_t *win, const FillArgs &A, i
     } else if (ACC == ACC_U16) {
         const int words = (W + 1) >> 1;
         if (A.merge == MERGE_STAGE) {
+            // the slot holds one byte per bin, bin 4i + k in byte k of word i;
+            // a counter above 255 stages 255 and adds the rest to the
+            // histogram itself (the bins past the window stage zeros)
             uint32_t *st = static_cast<uint32_t *>(A.stage) + (int64_t)col * A.stage_stride;
-            for (int i = threadIdx.x; i < words; i += blockDim.x)
-                st[i] = win[i];
+            const int swords = (W + 3) >> 2;
+            for (int i = threadIdx.x; i < swords; i += blockDim.x) {
+                const uint32_t v0 = win[2 * i];
+                const uint32_t v1 = 2 * i + 1 < words ? win[2 * i + 1] : 0u;
+                uint32_t c[4] = {v0 & 0xFFFFu, v0 >> 16, v1 & 0xFFFFu, v1 >> 16};
+                if ((v0 | v1) & 0xFF00FF00u) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (c[k] > 255u) {
+                            gl_add_u64(&A.cnt[A.win_lo + 4 * (int64_t)i + k], c[k] - 255u);
+                            c[k] = 255u;
+                        }
+                }
+                st[i] = c[0] | (c[1] << 8) | (c[2] << 16) | (c[3] << 24);
+            }
         } else {
             for (int i = threadIdx.x; i < words; i += blockDim.x) {
                 const uint32_t v = win[i];

@@ -127,12 +127,25 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
     const uint32_t wlo8 = (uint32_t)A.win_lo * (uint32_t)sizeof(double);
     const uint32_t len = (uint32_t)(end > start ? end - start : 0);
     const uint32_t step = (uint32_t)nthr * U;
-    __amdgpu_buffer_rsrc_t xb[1] = {column_rsrc(static_cast<const double *>(A.coords[0]) + start,
-                                                len * (uint32_t)sizeof(double))};
-    const __amdgpu_buffer_rsrc_t wb = column_rsrc(A.coords[0], 0u);
-    double cx[U][1], cw[U];
+    // A batch's loads go through a descriptor based at the batch and sized to
+    // what is left of the block's range (lanes past it read zero), so the
+    // per-lane offsets stay the same from batch to batch: the descriptor is
+    // advanced with scalar arithmetic and no load address is recomputed.
+    const double *col = static_cast<const double *>(A.coords[0]) + start;
+    uint32_t loff[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+        loff[j] = ((uint32_t)j * (uint32_t)nthr + (uint32_t)tid) * (uint32_t)sizeof(double);
+    double cx[U];
+    auto load_at = [&](uint32_t b) {
+        const uint32_t left = b < len ? (len - b) * (uint32_t)sizeof(double) : 0u;
+        const __amdgpu_buffer_rsrc_t r = column_rsrc(col + b, left);
+#pragma unroll
+        for (int j = 0; j < U; ++j)
+            cx[j] = buffer_load_nt<double>(r, loff[j]);
+    };
     if (len > 0)
-        load_batch<1, double, false, U>(xb, wb, 0, cx, cw);
+        load_at(0);
 
     double sx = 0.0, sxx = 0.0;
     uint32_t nok = 0, nflow = 0;   // events of this thread, and those out of range
@@ -145,10 +158,10 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
         double x[U];
 #pragma unroll
         for (int j = 0; j < U; ++j)
-            x[j] = cx[j][0];
+            x[j] = cx[j];
         // the next batch first: loads complete in issue order, so the edge
         // reads below wait for it in any case
-        load_batch<1, double, false, U>(xb, wb, base + step, cx, cw);
+        load_at(base + step);
         __builtin_amdgcn_sched_barrier(0);
 
         int32_t s[U];
@@ -177,17 +190,26 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
             // conversions cannot overflow (an infinite width gives NaN or
             // infinite differences, hence the wide marker)
             const float y = model_eval(m[j], z[j]);
-            const float fa = __builtin_ceilf(y);
-            const float d = __builtin_floorf(y + half_hi(m[j].cw)) - fa;   // bins in the interval - 1
-            const uint32_t tj = ((uint32_t)m[j].ai + (uint32_t)(int32_t)fa) << 1;
             const bool in = ok && !(x[j] < ax.xmin) && x[j] < ax.xmax;   // false for NaN
-            t[j] = !in ? kMarkOut : (!WIDE || d <= 1.0f) ? tj : kMarkWide;
-            const uint32_t eo = in && (WIDE ? d == 1.0f : d != 0.0f) ? 4u * tj + wlo8 : inf_off;
+            uint32_t tj;
+            bool two;   // the interval holds two bins
+            if (WIDE) {
+                const float fa = __builtin_ceilf(y);
+                const float d = __builtin_floorf(y + half_hi(m[j].cw)) - fa;   // bins in the interval - 1
+                tj = ((uint32_t)m[j].ai + (uint32_t)(int32_t)fa) << 1;
+                t[j] = !in ? kMarkOut : d <= 1.0f ? tj : kMarkWide;
+                two = d == 1.0f;
+            } else {
+                // widths below 2: both ends are integers near y, converted
+                // with floor (ceil(y) = -floor(-y))
+                const int32_t a = -(int32_t)__builtin_floorf(-y);
+                const int32_t b = (int32_t)__builtin_floorf(y + half_hi(m[j].cw));
+                tj = ((uint32_t)m[j].ai + (uint32_t)a) << 1;
+                t[j] = in ? tj : kMarkOut;
+                two = a != b;
+            }
+            const uint32_t eo = in && two ? 4u * tj + wlo8 : inf_off;
             e[j] = buffer_load_nt<double>(eb, eo);
-            // statistics sums of in-range events
-            const double xm = in ? x[j] : 0.0;
-            sx += xm;
-            sxx = __builtin_fma(xm, xm, sxx);
         }
         nok += FULL ? (uint32_t)U : 0u;
         if (!FULL) {
@@ -200,15 +222,23 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
         // path, which also takes flow events and searches the wide intervals.
 #pragma unroll
         for (int j = 0; j < U; ++j) {
+            // the statistics sums of in-range events are added under the
+            // same branches as their counters
             const uint32_t b2 = t[j] + (x[j] < e[j] ? 0u : 2u);
             const bool fast = b2 < wlen2;
-            if (fast)
+            if (fast) {
                 window_add(b2, 1u);
-            else if (FULL || base + (uint32_t)j * nthr + tid < len) {
+                sx += x[j];
+                sxx = __builtin_fma(x[j], x[j], sxx);
+            } else if (FULL || base + (uint32_t)j * nthr + tid < len) {
                 if ((b2 & ~31u) != kMarkOut) {        // in range, outside the window
                     spill<false>(A, smem, ((int32_t)b2 >> 1) + A.win_lo, 1.0);
+                    sx += x[j];
+                    sxx = __builtin_fma(x[j], x[j], sxx);
                 } else if (WIDE && b2 >= kMarkWide) {   // three or more candidate bins
                     lean_search_add(A, smem, win, x[j], 1, 0);
+                    sx += x[j];
+                    sxx = __builtin_fma(x[j], x[j], sxx);
                 } else {                                // flow
                     ++nflow;
                     spill<false>(A, smem, x[j] < ax.xmin ? 0 : ax.nbins + 1, 1.0);

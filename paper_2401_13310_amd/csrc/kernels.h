@@ -108,7 +108,7 @@ struct FillArgs {
     double *stats;            // [S]
     uint64_t *entries;        // entry count: the workgroup that starts at event 0 adds n
     void *stage;              // staging, one slot of stage_stride units per block
-    int64_t stage_stride;     // units per block: u32 words (U32/U16) or bins (F64/F32C)
+    int64_t stage_stride;     // units per block: u32 words (U32; U16: four 8-bit bins a word) or bins (F64/F32C)
     int32_t *gbins;           // TILED pass 1 / PCOUNT: global bin of every event
     uint32_t *part_table;     // PCOUNT: bucket-major counts table[bucket * gridDim.x + block]
     uint32_t *part_totals;    // PCOUNT: events per bucket (added to with atomics)

@@ -374,6 +374,47 @@ def test_fill_u16_counters_never_overflow(hg):
     assert sumw.sum() == n
 
 
+@pytest.mark.parametrize("learned", [False, True])
+def test_fill_u16_staged_merge_saturation(hg, learned):
+    """16-bit LDS counters merged through 8-bit staging slots: bins with more
+    than 255 (and more than 65535) events in a workgroup stage 255 and add the
+    rest directly; counts must stay exact either way."""
+    rng = np.random.default_rng(31)
+    n = 2_000_003
+    if learned:
+        axes = [{"nbins": 99_999, "edges": synth.log_edges(100_000)}]
+        x = rng.exponential(1.0, n)
+        x[: n // 3] = 0.5              # one bin, ~42k events per workgroup
+        x[n // 3: n // 3 + 40_000] = 2.0
+        x[-300:] = 1e-5                # underflow
+    else:
+        nb = 60_000
+        axes = [{"nbins": nb, "xmin": 0.0, "xmax": float(nb)}]
+        x = rng.uniform(-10.0, nb + 10.0, n)
+        x[: n // 3] = 12_345.5
+        x[n // 3: n // 3 + 40_000] = 17.25
+        x[n // 3 + 40_000: n // 3 + 45_000] = 59_999.0   # the window's last bin
+    rng.shuffle(x)
+    h = hg.Hist(axes)
+    if learned:
+        h.train_index(0)
+    assert h.plan_info(n)["accumulator"] == "u16"
+    h.set_strategy(hg.HIST_STRAT_LDS, 16, 0)
+    h.set_window(-1, 1)                 # staged merge
+    assert h.plan_info(n)["strategy"] == "lds"
+    h.timing(True)
+    for _ in range(2):
+        h.fill([dev(x)])
+    sumw, sumw2, entries = h.read()
+    assert h.timing_read()["merge_ms"] > 0.0      # the staged merge ran
+    o = oracle.Oracle(axes)
+    o.fill([np.concatenate([x, x])])
+    osw, _, _, oent = o.read()
+    assert entries == oent
+    assert_bins_equal(sumw, osw, "counts")
+    assert_bins_equal(sumw2, osw, "counts (sumw2)")
+
+
 def test_fill_precision_f32_compensated(hg):
     import torch
     axes = synth.precision_axes()
