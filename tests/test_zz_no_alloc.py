@@ -108,7 +108,8 @@ def test_static_rejects_oversized_staging(hg):
     lib = hg._lib.load()
     wl = synth.variable_1d(8_400_000)
     h = hg.Hist(wl["axes"], hg.HIST_F_NO_ALLOC)
-    h.set_strategy(hg.HIST_STRAT_LDS, 1024, 0)
+    # 4096 slots of one byte per bin of a window of more than 16384 bins
+    h.set_strategy(hg.HIST_STRAT_LDS, 4096, 0)
     h.set_window(0, 1)
     x = dev(wl["coords"][0])
     st = lib.hist_fill_static(h.handle, _ptrs([x]), None, x.numel(), hg.HIST_F64,
