@@ -653,7 +653,14 @@ extern "C" hist_status hist_tune(hist_t *h, const void *const *coords, const voi
             }
         }
     }
-    if (pb.strategy == HIST_STRAT_LDS || pb.strategy == HIST_STRAT_GLOBAL) {
+    // The events per thread of the general kernels.  A plan that runs the
+    // learned one-axis kernel keeps it: that kernel stages its model in every
+    // workgroup, a fixed cost that weighs more on a sample than on a full
+    // fill, so a sample can rank a general shape ahead of it that is slower
+    // at full size.
+    const bool lean = pb.strategy == HIST_STRAT_LDS && !pb.shape && pb.unroll == 8 &&
+                      learned_lean_supported(h->dims, f32, weighted, pb.acc, h->ax);
+    if ((pb.strategy == HIST_STRAT_LDS || pb.strategy == HIST_STRAT_GLOBAL) && !lean) {
         PlanChoice base = best;
         for (int u : {1, 2, 4, 8}) {
             PlanChoice c = base;
