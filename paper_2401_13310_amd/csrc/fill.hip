@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) stage_reduce_kernel(const FillArgs A, int
 
 // The 8-bit slots of the 16-bit windows: one workgroup per 64 consecutive
 // words (256 bins), its 256 threads 16 quads of words x 16 groups of slots,
-// 16-byte loads (slot strides are multiples of four words), every thread
+// 16-byte loads (slot strides are whole 128-byte lines), every thread
 // summing up to 16 slots.  Eight slots at a time are summed as 16-bit halves
 // (even and odd bytes apart, at most 8 x 255 each), then widened.  The partial
 // sums of each bin meet in LDS; one thread per bin adds the total.

@@ -64,8 +64,8 @@ int64_t stage_stride_for(const Plan &p)
 
 int64_t stage_stride_of(int acc, int64_t win_len)
 {
-    if (acc == ACC_U16)   // one byte per bin, in whole 16-byte quads of words
-        return ((win_len + 3) / 4 + 3) / 4 * 4;
+    if (acc == ACC_U16)   // one byte per bin, slots in whole 128-byte lines
+        return ((win_len + 3) / 4 + 31) / 32 * 32;
     return win_len;
 }
 
