@@ -118,7 +118,9 @@ typedef enum {
  * HIST_EDEVICE.  Synchronizes the device once (creation is not a hot call). */
 HIST_API hist_status hist_create(int dims, const hist_axis *axes, uint32_t flags, hist_t **out);
 
-/* Frees everything the handle owns.  NULL is accepted.  Synchronizes. */
+/* Frees everything the handle owns.  NULL is accepted.  Synchronizes.
+ * HIST_EINVAL, and nothing freed, while a live batch (hist_batch_create) or
+ * multi-fill set (hist_multi_create) holds the handle: destroy those first. */
 HIST_API hist_status hist_destroy(hist_t *h);
 
 /* ---- the hot path ---------------------------------------------------------- */
@@ -331,7 +333,9 @@ typedef struct {
  * set-up call and hist_batch_launch so that the set-up (tile lists, plans,
  * scratch, graph instantiation) is paid once and every launch is one graph
  * replay.  The inputs named in descs are bound into the graph: every
- * hist_batch_launch reads the same device buffers.  Allocates and
+ * hist_batch_launch reads the same device buffers, and they must stay
+ * allocated while the batch lives; the k handles are held by the batch
+ * (hist_destroy refuses them until hist_batch_destroy).  Allocates and
  * synchronizes.  Errors: HIST_EINVAL, HIST_ENOMEM, HIST_ECAPTURE. */
 HIST_API hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fill_desc *descs,
                               hist_batch_t **out, void *stream);
@@ -343,6 +347,8 @@ HIST_API hist_status hist_batch_launch(hist_batch_t *b, void *stream);
 /* Same work as one replay, launched directly without the graph. */
 HIST_API hist_status hist_batch_launch_eager(hist_batch_t *b, void *stream);
 
+/* Frees the batch and releases its handles (synchronizes the device).  NULL
+ * is accepted. */
 HIST_API hist_status hist_batch_destroy(hist_batch_t *b);
 
 /* ---- event filters, computed columns, several histograms per pass ----------- */
@@ -400,8 +406,9 @@ typedef struct {
  * Programs are checked here (operations, column indices, stack depth).  The
  * plan keeps each member's statistics, learned models and edge arrays of at
  * most 4,096 edges in LDS, then whole-histogram copies of the smallest members
- * while LDS lasts; other members take global atomics.  Handles must outlive
- * the plan; they may still be filled on their own.  Allocates and copies the
+ * while LDS lasts; other members take global atomics.  The handles are held
+ * by the plan (hist_destroy refuses them until hist_multi_destroy); they may
+ * still be filled on their own.  Allocates and copies the
  * plan to the device (synchronous).  Errors: HIST_EINVAL, HIST_ENOMEM,
  * HIST_EDEVICE. */
 HIST_API hist_status hist_multi_create(int k, hist_t *const *hs, const hist_define *defs, int ncols,

@@ -482,6 +482,7 @@ class Batch:
 
     def __init__(self, hists, coords_list, weights_list, stream=None):
         descs = []
+        self.hists = list(hists)   # every launch writes their sums: they live as long as the batch
         self._keep = []
         for h, coords, w in zip(hists, coords_list, weights_list):
             cols, n, dt = _check_cols(coords, w)

@@ -609,6 +609,8 @@ extern "C" hist_status hist_batch_create(int k, hist_t *const *hs, const hist_fi
         return set_error(e == hipErrorOutOfMemory ? HIST_ENOMEM : HIST_EDEVICE,
                          "hist_batch_create: %s", hipGetErrorString(e));
     }
+    for (hist_t *h : b->hs)
+        ++h->users;
     *out = b;
     return HIST_OK;
 }
@@ -646,6 +648,8 @@ extern "C" hist_status hist_batch_destroy(hist_batch_t *b)
     if (!b)
         return HIST_OK;
     (void)hipDeviceSynchronize();
+    for (hist_t *h : b->hs)
+        --h->users;
     batch_free(b);
     return HIST_OK;
 }

@@ -270,6 +270,10 @@ extern "C" hist_status hist_destroy(hist_t *h)
 {
     if (!h)
         return HIST_OK;
+    const int users = h->users.load();
+    if (users > 0)
+        return set_error(HIST_EINVAL, "hist_destroy: the handle is a member of %d live batch(es) or "
+                                      "multi-fill set(s); destroy those first", users);
     (void)hipDeviceSynchronize();
     free_handle(h);
     return HIST_OK;

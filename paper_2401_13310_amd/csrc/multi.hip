@@ -506,6 +506,7 @@ struct hist_multi_s {
     ExprOp *d_ops = nullptr;
     std::vector<MultiMember> members;
     std::vector<int> window_members;   // indices of members accumulated in LDS
+    std::vector<hist_t *> hs;          // the member handles (held: see hist_destroy)
 };
 
 // Checks a postfix program and records the stack depth before each operation.
@@ -764,6 +765,9 @@ extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_de
         return set_error(e == hipErrorOutOfMemory ? HIST_ENOMEM : HIST_EDEVICE,
                          "hist_multi_create: %s", hipGetErrorString(e));
     }
+    M->hs.assign(hs, hs + k);
+    for (hist_t *h : M->hs)
+        ++h->users;
     *out = M;
     return HIST_OK;
 }
@@ -847,6 +851,8 @@ extern "C" hist_status hist_multi_destroy(hist_multi_t *M)
     if (!M)
         return HIST_OK;
     (void)hipDeviceSynchronize();
+    for (hist_t *h : M->hs)
+        --h->users;
     free_multi(M);
     return HIST_OK;
 }

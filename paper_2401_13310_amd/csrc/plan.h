@@ -4,6 +4,7 @@
 #include "../../include/hist.h"
 #include "kernels.h"
 
+#include <atomic>
 #include <map>
 #include <string>
 #include <tuple>
@@ -96,6 +97,9 @@ struct hist_s {
     int ev_next = 0;
     std::map<std::tuple<int, int, int>, hg::PlanChoice> tuned;  // (acc, f32, n bucket)
     hg::HostStreamer *host = nullptr;                    // hist_fill_host buffers and copy stream
+    // live batches and multi-fill sets that write into this handle's sums:
+    // hist_destroy refuses the handle while any holds it
+    std::atomic<int> users{0};
 };
 
 namespace hg {

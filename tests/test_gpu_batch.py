@@ -172,3 +172,29 @@ def test_batch_rejects_bad_arguments(hg):
     x = dev(np.zeros(10))
     with pytest.raises(hg.HistError):
         hg.Batch([h, h], [[x], [x]], [None, None])
+
+
+def test_batch_holds_its_histograms(hg):
+    """A batch keeps its histograms alive (the caller may drop them), and the
+    library refuses to destroy a handle while a live batch holds it."""
+    import gc
+    import torch
+    members = make_members(2e-3, k=6, seed=5)
+
+    def batch_only():
+        hists, cols, ws = build(hg, members)
+        return hg.Batch(hists, cols, ws)
+
+    b = batch_only()
+    gc.collect()
+    b.launch()
+    torch.cuda.synchronize()
+    for h, m in zip(b.hists, members):
+        check_member(h, m)
+    lib = hg._lib.load()
+    assert lib.hist_destroy(b.hists[0].handle) == hg._lib.HIST_EINVAL
+    assert b"live batch" in lib.hist_last_error()
+    hists = b.hists
+    b.close()
+    for h in hists:
+        h.close()                          # released with the batch

@@ -205,3 +205,13 @@ def test_invalid_programs_are_rejected(hg):
             hg.Multi([h], [{"coords": [ops]}], ["x", "y"])
     with pytest.raises(hg.HistError):
         hg.Multi([h, h], None, ["x"])                          # repeated handle
+
+
+def test_multi_holds_its_histograms(hg):
+    """hist_destroy refuses a handle a live multi-fill set holds."""
+    h = hg.Hist([{"nbins": 10, "xmin": 0.0, "xmax": 1.0}])
+    plan = hg.Multi([h], None, ["x"])
+    lib = hg._lib.load()
+    assert lib.hist_destroy(h.handle) == hg._lib.HIST_EINVAL
+    plan.close()
+    h.close()
