@@ -283,6 +283,14 @@ def to_dev(wl):
     return cols, w
 
 
+# Events of the autotuner's sample: enough for the full-size plan's workgroups
+# to run several iterations of their loop.  On 2^22 events the learned fill's
+# 255 workgroups ran two, where fixed per-workgroup costs dominate, and the
+# tuner at times ranked 512-thread workgroups first although they are 12%
+# slower on the 5e7-event fill.
+TUNE_SAMPLE = 1 << 24
+
+
 def train_all(h, axes):
     for a, ax in enumerate(axes):
         if ax.get("edges") is not None:
@@ -347,7 +355,7 @@ def config_single(name, wl, args, threads, flags=0, compare_global=False):
     n = wl["coords"][0].size
     h = hg.Hist(wl["axes"], flags)
     train_all(h, wl["axes"])
-    sample = min(n, 1 << 22)
+    sample = min(n, TUNE_SAMPLE)
     if args.strategy == "tuned":
         h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
     else:
@@ -683,7 +691,7 @@ def run_single(args, wl, headline):
         train_all(h, wl["axes"])
         torch.cuda.synchronize()
         train_ms = (time.perf_counter() - t0) * 1e3
-    sample = min(n, 1 << 22)
+    sample = min(n, TUNE_SAMPLE)
     if args.strategy == "tuned":
         h.tune([c[:sample] for c in cols], None if w is None else w[:sample])
     else:

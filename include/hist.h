@@ -283,7 +283,8 @@ HIST_API hist_status hist_plan_info(hist_t *h, int64_t n, hist_dtype dtype, int 
 HIST_API hist_status hist_set_window(hist_t *h, int64_t window_lo, int merge);
 
 /* Fixes the threads per workgroup of later fills (0 = heuristic; 256, 512 or
- * 1024).  Used by tests and benchmarks to pin a plan. */
+ * 1024), also over a plan hist_tune chose.  Used by tests and benchmarks to
+ * pin a plan. */
 HIST_API hist_status hist_set_threads(hist_t *h, int threads);
 
 /* Launch shape of later fills (the paper's tuning study, Sec. 4.3, varies the

@@ -324,7 +324,10 @@ Plan make_plan(const hist_s *h, int64_t n, hist_dtype dtype, bool weighted)
             if (jt != g_cache.end())
                 c = jt->second;
         }
-        // a shape fixed by hist_set_shape applies over a tuned choice
+        // a shape fixed by hist_set_shape or hist_set_threads applies over
+        // a tuned choice
+        if (h->forced.threads > 0)
+            c.threads = h->forced.threads;
         if (h->forced.unroll > 0)
             c.unroll = h->forced.unroll;
         if (h->forced.stats_ept > 0)
