@@ -297,14 +297,14 @@ __device__ __forceinline__ void part_accum_chunk(uint32_t t, const uint32_t *buc
     for (int i = tid; i < words; i += nthr)
         c32[i] = 0u;
     __syncthreads();
-    // records in groups of four from the first 4-aligned record (an 8-byte
-    // load of the offsets, two 16-byte loads of the weights), the unaligned
-    // head and the tail one at a time
+    // records four at a time (8-byte loads of offsets) from the first
+    // 4-aligned record; the unaligned head and the tail one at a time
     const uint32_t r0a = (r0 + 3u) & ~3u;
     const uint32_t a0 = r0a < r1 ? r0a : r1;
     const uint32_t a1 = a0 + ((r1 - a0) & ~3u);
-    auto addw = [&](uint32_t l, double wv) {
+    auto add = [&](uint32_t r, uint32_t l) {
         if (W) {
+            const double wv = rec_w[r];
             lds_add_f64(&s64[l], wv);
             lds_add_f64(&s64[len + l], wv * wv);
         } else {
@@ -312,38 +312,16 @@ __device__ __forceinline__ void part_accum_chunk(uint32_t t, const uint32_t *buc
         }
     };
     for (uint32_t r = r0 + tid; r < a0; r += nthr)
-        addw(rec_off[r], W ? rec_w[r] : 0.0);
-    // a thread's groups are a workgroup apart; kGroups of them are loaded
-    // before any is added, so their loads overlap
-    constexpr int kGroups = 4;
-    for (uint32_t r = a0 + 4u * tid; r < a1; r += 4u * kGroups * nthr) {
-        uint2 q[kGroups];
-        double2 wa[kGroups], wb[kGroups];
-        bool v[kGroups];
-#pragma unroll
-        for (int k = 0; k < kGroups; ++k) {
-            const uint32_t rk = r + 4u * (uint32_t)k * nthr;
-            v[k] = rk < a1;   // then rk + 3 < a1 too: both are a0 plus a multiple of 4
-            if (v[k]) {
-                q[k] = *reinterpret_cast<const uint2 *>(rec_off + rk);
-                if (W) {
-                    wa[k] = *reinterpret_cast<const double2 *>(rec_w + rk);
-                    wb[k] = *reinterpret_cast<const double2 *>(rec_w + rk + 2);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kGroups; ++k) {
-            if (v[k]) {
-                addw(q[k].x & 0xFFFFu, W ? wa[k].x : 0.0);
-                addw(q[k].x >> 16, W ? wa[k].y : 0.0);
-                addw(q[k].y & 0xFFFFu, W ? wb[k].x : 0.0);
-                addw(q[k].y >> 16, W ? wb[k].y : 0.0);
-            }
-        }
+        add(r, rec_off[r]);
+    for (uint32_t r = a0 + 4u * tid; r < a1; r += 4u * nthr) {
+        const uint2 q = *reinterpret_cast<const uint2 *>(rec_off + r);
+        add(r, q.x & 0xFFFFu);
+        add(r + 1, q.x >> 16);
+        add(r + 2, q.y & 0xFFFFu);
+        add(r + 3, q.y >> 16);
     }
     for (uint32_t r = a1 + tid; r < r1; r += nthr)
-        addw(rec_off[r], W ? rec_w[r] : 0.0);
+        add(r, rec_off[r]);
     __syncthreads();
     for (int l = tid; l < len; l += nthr) {
         if (W) {
