@@ -200,13 +200,14 @@ __global__ void __launch_bounds__(kMaxThreads) fill_learned_kernel(const FillArg
                 t[j] = !in ? kMarkOut : d <= 1.0f ? tj : kMarkWide;
                 two = d == 1.0f;
             } else {
-                // widths below 2: both ends are integers near y, converted
-                // with floor (ceil(y) = -floor(-y))
-                const int32_t a = -(int32_t)__builtin_floorf(-y);
-                const int32_t b = (int32_t)__builtin_floorf(y + half_hi(m[j].cw));
-                tj = ((uint32_t)m[j].ai + (uint32_t)a) << 1;
+                // widths below 2: the ends are integers near y, ceil(y) taken
+                // as -floor(-y); only the lower one is converted, the two are
+                // compared as floats (exact for integers of this size)
+                const float na = __builtin_floorf(-y);
+                const float b = __builtin_floorf(y + half_hi(m[j].cw));
+                tj = ((uint32_t)m[j].ai - (uint32_t)(int32_t)na) << 1;
                 t[j] = in ? tj : kMarkOut;
-                two = a != b;
+                two = b != -na;
             }
             const uint32_t eo = in && two ? 4u * tj + wlo8 : inf_off;
             e[j] = buffer_load_nt<double>(eb, eo);
