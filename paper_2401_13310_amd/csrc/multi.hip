@@ -65,8 +65,7 @@ struct MultiMember {
     int32_t weight_col;            // weight column, -1: program or unit weights
     int32_t weighted;              // a weight program or column
     int32_t lean;                  // one fixed-width axis read from a column, unit weights, no
-                                   // filter, LDS copy: the short path, with per-thread sums
-                                   // in LDS (1) or in registers (2)
+                                   // filter, LDS copy and per-thread sums: the short path
     uint64_t *cnt;
     double *sumw, *sumw2, *stats;
     uint64_t *entries;
@@ -77,10 +76,6 @@ struct MultiMember {
 using ConstMultiMember = __attribute__((address_space(4))) const MultiMember;
 using ConstExprOp = __attribute__((address_space(4))) const ExprOp;
 
-// Plain projections (`lean` members) whose sums stay in registers: the first
-// kLeanRegs of them; any others use per-thread LDS sums.
-constexpr int kLeanRegs = 4;
-
 struct MultiArgs {
     const MultiMember *members;
     const ExprOp *ops;
@@ -89,8 +84,6 @@ struct MultiArgs {
     int32_t ncols;
     int64_t n;
     int64_t per_block;
-    int32_t nlean;                  // members in lean_idx
-    int32_t lean_idx[kLeanRegs];    // lean members whose sums are kept in registers
 };
 
 // ---------------------------------------------------------------- programs --
@@ -283,17 +276,6 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
     };
     if (start < end)
         load_batch(start);
-    // the register-held plain projections: sums of x and x^2 and the counts
-    // of events and of in-range events of this thread
-    double lsx[kLeanRegs], lsxx[kLeanRegs];
-    uint32_t lnk[kLeanRegs], lni[kLeanRegs];
-#pragma unroll
-    for (int q = 0; q < kLeanRegs; ++q) {
-        lsx[q] = 0.0;
-        lsxx[q] = 0.0;
-        lnk[q] = 0u;
-        lni[q] = 0u;
-    }
     for (int64_t base = start; base < end; base += (int64_t)nthr * U) {
         dvec8 cv = 0.0;
         bool ok[U];
@@ -305,29 +287,8 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
             cv[c] = (double)nv[c][0];
         if (base + (int64_t)nthr * U < end)
             load_batch(base + (int64_t)nthr * U);
-#pragma unroll
-        for (int q = 0; q < kLeanRegs; ++q) {
-            if (q < A.nlean) {
-                const MultiMember &M = *(const MultiMember *)&mem[A.lean_idx[q]];
-                const double xs[1] = {cv[M.coord_col[0]]};
-                int32_t b[1];
-                bool inr[1];
-                bins_uniform<1>(xs, M.ax[0], b, inr);
-                if (ok[0])
-                    lds_add_u32(reinterpret_cast<uint32_t *>(smem + M.lds_win) +
-                                    ((uint32_t)b[0] * (uint32_t)M.copies + (uint32_t)(tid % M.copies)), 1u);
-                const bool take = ok[0] && inr[0];
-                lnk[q] += ok[0] ? 1u : 0u;
-                lni[q] += take ? 1u : 0u;
-                const double xm = take ? xs[0] : 0.0;
-                lsx[q] += xm;
-                lsxx[q] += xm * xm;
-            }
-        }
         for (int m = 0; m < A.k; ++m) {
             const MultiMember &M = *(const MultiMember *)&mem[m];
-            if (M.lean == 2)   // held in registers above
-                continue;
             if (M.lean) {
                 // a plain projection: bin, count in LDS, sums of x and x^2
                 const double xs[1] = {cv[M.coord_col[0]]};
@@ -471,31 +432,6 @@ __global__ void __launch_bounds__(kMaxThreads) multi_fill_kernel(const MultiArgs
             }
         }
     }
-    // the register-held projections' sums into their per-thread LDS slots, and
-    // their counts (summed over the wave first)
-#pragma unroll
-    for (int q = 0; q < kLeanRegs; ++q) {
-        if (q < A.nlean) {
-            const MultiMember &M = *(const MultiMember *)&mem[A.lean_idx[q]];
-            double *ts = reinterpret_cast<double *>(smem + M.lds_tstats) + tid;
-            ts[0] = lsx[q];
-            ts[nthr] = lsxx[q];
-            uint32_t nk = lnk[q], ni = lni[q];
-#pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1) {
-                nk += __shfl_down(nk, off, kWave);
-                ni += __shfl_down(ni, off, kWave);
-            }
-            if ((tid & (kWave - 1)) == 0) {
-                uint32_t *lcnt = reinterpret_cast<uint32_t *>(reinterpret_cast<double *>(smem + M.lds_stats) +
-                                                              kMaxStats);
-                if (nk)
-                    lds_add_u32(&lcnt[0], nk);
-                if (ni)
-                    lds_add_u32(&lcnt[1], ni);
-            }
-        }
-    }
     __syncthreads();
     // per-thread sums -> the member's statistics partials (once per block)
     for (int m = 0; m < A.k; ++m) {
@@ -571,7 +507,6 @@ struct hist_multi_s {
     std::vector<MultiMember> members;
     std::vector<int> window_members;   // indices of members accumulated in LDS
     std::vector<hist_t *> hs;          // the member handles (held: see hist_destroy)
-    std::vector<int32_t> lean_regs;    // members whose sums the kernel keeps in registers
 };
 
 // Checks a postfix program and records the stack depth before each operation.
@@ -814,11 +749,6 @@ extern "C" hist_status hist_multi_create(int k, hist_t *const *hs, const hist_de
         MultiMember &d = M->members[i];
         d.lean = d.dims == 1 && d.ax[0].kind == AX_UNIFORM && d.filter.nops == 0 &&
                  d.coord[0].nops == 0 && !d.weighted && d.lds_win >= 0 && d.lds_tstats >= 0;
-        // the first kLeanRegs plain projections keep their sums in registers
-        if (d.lean && (int)M->lean_regs.size() < kLeanRegs) {
-            d.lean = 2;
-            M->lean_regs.push_back(i);
-        }
     }
     M->lds = std::max(off, 16);
 
@@ -865,9 +795,6 @@ extern "C" hist_status hist_multi_fill(hist_multi_t *M, const void *const *colum
     a.k = M->k;
     a.ncols = M->ncols;
     a.n = n;
-    a.nlean = (int32_t)M->lean_regs.size();
-    for (int q = 0; q < a.nlean; ++q)
-        a.lean_idx[q] = M->lean_regs[(size_t)q];
     const int threads = kMaxThreads;
     const int64_t step = (int64_t)threads * kMultiU;
     int64_t G = M->num_cu;
